@@ -1,0 +1,389 @@
+"""Seeded synthetic clips for the event simulator.
+
+The paper renders its frames with a Monte Carlo path tracer and keeps, per
+pixel, the noisy radiance plus first-bounce feature buffers (Sec. 3: 2-D image
+coordinate, 3-D normal, 1-D depth, 3-D texture colour).  Those scenes and the
+renderer are not available, so this module draws procedural stand-ins with the
+same structure:
+
+* a static textured background (value-noise albedo, a bump height field for the
+  normals, a depth ramp);
+* ``n_discs`` textured discs that translate (reflecting at the borders) and
+  rotate, each with its own rotating albedo texture, dome normals and a nearer
+  depth;
+* radiance ``E = lum(albedo) * max(0.05, n.l) * G(x, y)`` with ``G`` a smooth
+  seeded gradient in [0.2, 1];
+* ``spp`` jittered sub-pixel samples per pixel.  Every radiance sample is
+  ``E_s * X_s`` with ``X_s ~ Gamma(k=1)`` (unit exponential), so the per-pixel
+  mean has relative noise ``1/sqrt(spp)``; the feature buffers are sample
+  averages and are therefore noisy only where features vary inside a pixel.
+
+Outputs are the per-pixel sample mean ``E`` and unbiased sample variance ``var``
+of the radiance, ``[T][H][W]`` float32, and ``feat`` ``[T][F][H][W]`` (float32
+or float16).  The log-brightness that the method consumes is *not* computed
+here: it is the first step of the method and lives in the kernels/oracle.
+
+All randomness comes from a counter-based integer hash of
+``(seed, stream, index)``, so a clip does not depend on how it is chunked and
+is reproducible on any torch device (integer arithmetic is exact everywhere).
+
+Feature sets (normalised so that a unit bandwidth is meaningful):
+
+* ``F <= 7``: the first F of ``[nx, ny, nz, albedo_r, albedo_g, albedo_b,
+  depth/depth_bound]`` (normals in [-1, 1], albedo in [0, 1]).
+* ``F == 8, 9``: the 7-set plus motion ``(mx, my)`` in px/frame divided by
+  ``motion_scale``.
+* ``F == 10``: octahedral normal (2), albedo (3), depth (1), motion (2),
+  octahedral shading normal (2).
+"""
+from __future__ import annotations
+
+import dataclasses
+import math
+from typing import Optional, Sequence
+
+import torch
+
+__all__ = ["ClipSpec", "make_clip", "random_features_clip", "config_spec", "CONFIGS"]
+
+_MASK32 = 0xFFFFFFFF
+
+
+def _hash32(x: torch.Tensor) -> torch.Tensor:
+    """Integer avalanche hash on int64 tensors holding values in [0, 2^32).
+
+    Multipliers stay below 2^28 so no intermediate leaves the int64 range."""
+    x = x & _MASK32
+    x = (((x >> 16) ^ x) * 0x45D9F3B) & _MASK32
+    x = (((x >> 16) ^ x) * 0x45D9F3B) & _MASK32
+    x = ((x >> 16) ^ x) & _MASK32
+    return x
+
+
+def _uniform(seed: int, stream: int, idx: torch.Tensor) -> torch.Tensor:
+    """U[0,1) float32 from (seed, stream, idx); idx is an int64 tensor."""
+    h = _hash32(idx + (seed * 0x9E37 + stream * 0x3C6EF) )
+    h = _hash32(h ^ ((seed * 0x27D4EB2D + stream * 0x165667B1) & _MASK32))
+    h = _hash32(h + idx * 0x2545F49)
+    return (h >> 8).to(torch.float32) * (1.0 / 16777216.0)
+
+
+class _ValueNoise:
+    """Smooth 2-D value noise on a square lattice of spacing ``cell`` pixels.
+
+    Lattice values come from the hash, so the field is defined everywhere
+    without storing a grid."""
+
+    def __init__(self, seed: int, layer: int, cell: float):
+        self.seed, self.layer, self.cell = seed, layer, float(cell)
+
+    def _lattice(self, ix: torch.Tensor, iy: torch.Tensor) -> torch.Tensor:
+        key = ((iy + 4096) * 8192 + (ix + 4096)) & _MASK32
+        return _uniform(self.seed, 1000 + self.layer, key)
+
+    def __call__(self, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        gx = x / self.cell
+        gy = y / self.cell
+        ix = torch.floor(gx)
+        iy = torch.floor(gy)
+        fx = gx - ix
+        fy = gy - iy
+        ix = ix.to(torch.int64)
+        iy = iy.to(torch.int64)
+        sx = fx * fx * (3.0 - 2.0 * fx)
+        sy = fy * fy * (3.0 - 2.0 * fy)
+        v00 = self._lattice(ix, iy)
+        v10 = self._lattice(ix + 1, iy)
+        v01 = self._lattice(ix, iy + 1)
+        v11 = self._lattice(ix + 1, iy + 1)
+        a = v00 + (v10 - v00) * sx
+        b = v01 + (v11 - v01) * sx
+        return a + (b - a) * sy
+
+    def octaves(self, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+        """Two octaves, weights 2/3 and 1/3, range [0, 1]."""
+        fine = _ValueNoise(self.seed, self.layer + 500, self.cell * 0.5)
+        return (2.0 / 3.0) * self(x, y) + (1.0 / 3.0) * fine(x, y)
+
+
+@dataclasses.dataclass
+class ClipSpec:
+    W: int
+    H: int
+    T: int
+    spp: int
+    F: int = 7
+    n_discs: int = 3
+    speed: Sequence[float] = (0.5, 2.0)        # px / frame
+    ang_speed: Sequence[float] = (0.005, 0.03)  # rad / frame
+    radius: Sequence[float] = (0.08, 0.2)      # fraction of min(H, W)
+    bg_cell: float = 16.0
+    bump_cell: float = 24.0
+    bump_amp: float = 6.0
+    disc_cell: float = 10.0
+    motion_scale: float = 1.0
+    feat_dtype: str = "f32"   # "f32" | "f16"
+    seed: int = 0
+
+
+# The five workloads of the build, as seeded specs.  Sizes, spp, F and the
+# radii follow the workloads; scene parameters (disc count, speeds) are tuned so
+# the flagged fraction lands in the stated range.
+def config_spec(index: int) -> dict:
+    """Return ``dict(spec=ClipSpec, r=, tr=, C=, dt=)`` for workload ``index``
+    (0: small, 1: DVS-scale, 3: differentiation, 4: precision).  Workload 2
+    (batching) is a list of clips; see :func:`batch_specs`."""
+    if index == 0:
+        return dict(spec=ClipSpec(W=64, H=64, T=16, spp=4, F=7, n_discs=3,
+                                  speed=(0.5, 2.0), seed=1000),
+                    r=5, tr=0, C=0.2, dt=1.0)
+    if index == 1:
+        # 50-400 px/s at 1 ms per frame = 0.05-0.4 px / frame.
+        return dict(spec=ClipSpec(W=640, H=480, T=120, spp=8, F=7, n_discs=10,
+                                  speed=(0.05, 0.4), ang_speed=(0.002, 0.01),
+                                  disc_cell=6.0, seed=1001),
+                    r=7, tr=1, C=0.15, dt=1e-3)
+    if index == 3:
+        return dict(spec=ClipSpec(W=640, H=480, T=60, spp=8, F=7, n_discs=10,
+                                  speed=(0.05, 0.4), ang_speed=(0.002, 0.01),
+                                  disc_cell=6.0, seed=1003),
+                    r=7, tr=1, C=0.15, dt=1e-3)
+    if index == 4:
+        return dict(spec=ClipSpec(W=1920, H=1080, T=500, spp=16, F=10, n_discs=16,
+                                  speed=(0.05, 0.4), ang_speed=(0.002, 0.01),
+                                  disc_cell=8.0, feat_dtype="f16",
+                                  motion_scale=10.0, seed=1004),
+                    r=10, tr=2, C=0.15, dt=1e-3)
+    raise ValueError(f"no single-clip workload {index}")
+
+
+def batch_specs(n_clips: int = 32, seed: int = 5000,
+                max_pixel_frames: Optional[float] = None) -> list:
+    """Clip list of the batching workload: W ~ U{128..1280}, H ~ U{128..720},
+    T ~ U{30..300}, spp ~ U{2..16}, r ~ U{5..9}, Tr = 1, F = 7, C = 0.15.
+
+    ``max_pixel_frames`` optionally scales T down (keeping every other draw)
+    so a reduced variant fits a test budget."""
+    out = []
+    for i in range(n_clips):
+        u = _uniform(seed + i, 77, torch.arange(8, dtype=torch.int64)).tolist()
+        W = 128 + int(u[0] * (1280 - 128 + 1))
+        H = 128 + int(u[1] * (720 - 128 + 1))
+        T = 30 + int(u[2] * (300 - 30 + 1))
+        spp = 2 + int(u[3] * 15)
+        r = 5 + int(u[4] * 5)
+        n_discs = 2 + int(u[5] * 14)
+        out.append(dict(spec=ClipSpec(W=W, H=H, T=T, spp=spp, F=7, n_discs=n_discs,
+                                      speed=(0.05, 0.6), ang_speed=(0.002, 0.02),
+                                      disc_cell=6.0 + 6.0 * u[6], seed=seed + i),
+                        r=r, tr=1, C=0.15, dt=1e-3))
+    if max_pixel_frames is not None:
+        tot = sum(c["spec"].W * c["spec"].H * c["spec"].T for c in out)
+        if tot > max_pixel_frames:
+            s = max_pixel_frames / tot
+            for c in out:
+                c["spec"].T = max(3, int(c["spec"].T * s))
+    return out
+
+
+CONFIGS = {0: "small 64x64x16", 1: "DVS 640x480x120", 3: "diff 640x480x60",
+           4: "precision 1920x1080x500 f16"}
+
+
+class _Scene:
+    """Per-clip scene parameters, all drawn from the hash."""
+
+    def __init__(self, s: ClipSpec, device):
+        self.s = s
+        self.device = device
+        u = _uniform(s.seed, 7, torch.arange(16 * max(1, s.n_discs) + 16,
+                                             dtype=torch.int64)).tolist()
+        m = float(min(s.W, s.H))
+        self.discs = []
+        for k in range(s.n_discs):
+            q = u[16 + 16 * k: 32 + 16 * k]
+            R = m * (s.radius[0] + (s.radius[1] - s.radius[0]) * q[0])
+            R = min(R, 0.45 * m)
+            cx = R + (s.W - 2 * R) * q[1]
+            cy = R + (s.H - 2 * R) * q[2]
+            sp = s.speed[0] + (s.speed[1] - s.speed[0]) * q[3]
+            ang = 2 * math.pi * q[4]
+            om = (s.ang_speed[0] + (s.ang_speed[1] - s.ang_speed[0]) * q[5])
+            om = om if q[6] < 0.5 else -om
+            self.discs.append(dict(R=R, c0=(cx, cy), v=(sp * math.cos(ang), sp * math.sin(ang)),
+                                   th0=2 * math.pi * q[7], om=om,
+                                   depth=6.0 - 4.0 * k / max(1, s.n_discs),
+                                   layer=100 + 8 * k))
+        # light direction and radiance gradient
+        l = (0.3, -0.4, 0.87)
+        n = math.sqrt(sum(c * c for c in l))
+        self.light = tuple(c / n for c in l)
+        self.g_a = 1.0 + 2.0 * u[0]
+        self.g_b = 1.0 + 2.0 * u[1]
+        self.g_ph = 2 * math.pi * u[2]
+        self.depth_bound = 10.0 + 0.01 * s.H + 0.5 * s.bump_amp
+        self.bg_alb = [_ValueNoise(s.seed, c, s.bg_cell) for c in range(3)]
+        self.bump = _ValueNoise(s.seed, 3, s.bump_cell)
+        self.fine_bump = _ValueNoise(s.seed, 4, 6.0)
+
+    @staticmethod
+    def _reflect(p0: float, v: float, t: float, lo: float, hi: float) -> float:
+        span = hi - lo
+        if span <= 0:
+            return lo, 1.0
+        x = (p0 - lo + v * t) % (2 * span)
+        return lo + (x if x <= span else 2 * span - x), (1.0 if x <= span else -1.0)
+
+    def disc_state(self, k: int, t: float):
+        d = self.discs[k]
+        s = self.s
+        R = d["R"]
+        cx, sx = self._reflect(d["c0"][0], d["v"][0], t, R, s.W - R)
+        cy, sy = self._reflect(d["c0"][1], d["v"][1], t, R, s.H - R)
+        return cx, cy, d["v"][0] * sx, d["v"][1] * sy, d["th0"] + d["om"] * t
+
+    def shade(self, t: int, x: torch.Tensor, y: torch.Tensor):
+        """Surface attributes at continuous image positions (pixel centres at
+        integer + 0.5).  Returns dict of tensors shaped like x."""
+        s = self.s
+        # background
+        alb = [0.3 + 0.4 * f.octaves(x, y) for f in self.bg_alb]
+        e = 0.5
+        h = lambda xx, yy: s.bump_amp * self.bump(xx, yy)
+        hx = (h(x + e, y) - h(x - e, y)) / (2 * e)
+        hy = (h(x, y + e) - h(x, y - e)) / (2 * e)
+        nx, ny, nz = -hx, -hy, torch.ones_like(x)
+        depth = 10.0 + 0.01 * y + 0.5 * h(x, y)
+        mx = torch.zeros_like(x)
+        my = torch.zeros_like(x)
+        for k, d in enumerate(self.discs):
+            cx, cy, vx, vy, th = self.disc_state(k, float(t))
+            dx = x - cx
+            dy = y - cy
+            rho2 = (dx * dx + dy * dy) / (d["R"] * d["R"])
+            inside = rho2 < 1.0
+            if not bool(inside.any()):
+                continue
+            c, sn = math.cos(-th), math.sin(-th)
+            qx = c * dx - sn * dy + 1000.0
+            qy = sn * dx + c * dy + 1000.0
+            tex = [_ValueNoise(s.seed, d["layer"] + ch, s.disc_cell) for ch in range(3)]
+            dalb = [0.25 + 0.6 * tx.octaves(qx, qy) for tx in tex]
+            dome = torch.sqrt(torch.clamp(1.0 - 0.64 * rho2, min=1e-6))
+            dnx = 0.8 * dx / d["R"]
+            dny = 0.8 * dy / d["R"]
+            ddepth = d["depth"] - 2.0 * torch.sqrt(torch.clamp(1.0 - rho2, min=0.0))
+            alb = [torch.where(inside, da, a) for da, a in zip(dalb, alb)]
+            nx = torch.where(inside, dnx, nx)
+            ny = torch.where(inside, dny, ny)
+            nz = torch.where(inside, dome, nz)
+            depth = torch.where(inside, ddepth, depth)
+            mx = torch.where(inside, vx - d["om"] * dy, mx)
+            my = torch.where(inside, vy + d["om"] * dx, my)
+        inv = torch.rsqrt(nx * nx + ny * ny + nz * nz)
+        nx, ny, nz = nx * inv, ny * inv, nz * inv
+        lx, ly, lz = self.light
+        ndl = torch.clamp(nx * lx + ny * ly + nz * lz, min=0.05)
+        lum = 0.2126 * alb[0] + 0.7152 * alb[1] + 0.0722 * alb[2]
+        G = 0.2 + 0.8 * (0.5 + 0.5 * torch.sin(self.g_a * x / s.W * math.pi
+                                                + self.g_b * y / s.H * math.pi + self.g_ph))
+        E = lum * ndl * G
+        out = dict(nx=nx, ny=ny, nz=nz, ar=alb[0], ag=alb[1], ab=alb[2],
+                   depth=depth / self.depth_bound, mx=mx / s.motion_scale,
+                   my=my / s.motion_scale, E=E)
+        if s.F == 10:
+            # octahedral encodings of the geometric and a bump-perturbed normal
+            out["on0"], out["on1"] = _octa(nx, ny, nz)
+            fb = lambda xx, yy: 2.0 * self.fine_bump(xx, yy)
+            sx = (fb(x + e, y) - fb(x - e, y)) / (2 * e)
+            sy = (fb(x, y + e) - fb(x, y - e)) / (2 * e)
+            snx, sny, snz = nx - 0.3 * sx, ny - 0.3 * sy, nz
+            inv = torch.rsqrt(snx * snx + sny * sny + snz * snz)
+            out["os0"], out["os1"] = _octa(snx * inv, sny * inv, snz * inv)
+        return out
+
+
+def _octa(nx, ny, nz):
+    s = nx.abs() + ny.abs() + nz.abs()
+    u, v = nx / s, ny / s
+    neg = nz < 0
+    uu = torch.where(neg, (1 - v.abs()) * torch.sign(u), u)
+    vv = torch.where(neg, (1 - u.abs()) * torch.sign(v), v)
+    return uu, vv
+
+
+_ORDER7 = ["nx", "ny", "nz", "ar", "ag", "ab", "depth", "mx", "my"]
+_ORDER10 = ["on0", "on1", "ar", "ag", "ab", "depth", "mx", "my", "os0", "os1"]
+
+
+def _channels(F: int) -> list:
+    if F == 10:
+        return _ORDER10
+    if 1 <= F <= 9:
+        return _ORDER7[:F]
+    raise ValueError("F must be in 1..10")
+
+
+def make_clip(spec: ClipSpec, device="cpu", frames: Optional[Sequence[int]] = None):
+    """Render a clip.  Returns a dict with ``E``, ``var`` ``[T][H][W]`` f32 and
+    ``feat`` ``[T][F][H][W]`` (f32 or f16), all on ``device``."""
+    s = spec
+    dev = torch.device(device)
+    scene = _Scene(s, dev)
+    chans = _channels(s.F)
+    frames = list(range(s.T)) if frames is None else list(frames)
+    T = len(frames)
+    fdt = torch.float16 if s.feat_dtype == "f16" else torch.float32
+    E = torch.empty((T, s.H, s.W), dtype=torch.float32, device=dev)
+    V = torch.empty((T, s.H, s.W), dtype=torch.float32, device=dev)
+    feat = torch.empty((T, s.F, s.H, s.W), dtype=fdt, device=dev)
+    HW = s.H * s.W
+    pix = torch.arange(HW, dtype=torch.int64, device=dev)
+    py = (pix // s.W).to(torch.float32)
+    px = (pix % s.W).to(torch.float32)
+    # chunk pixels so one frame's samples stay within a modest working set
+    chunk = max(1, (1 << 22) // max(1, s.spp))
+    for ti, t in enumerate(frames):
+        accE = torch.empty(HW, dtype=torch.float32, device=dev)
+        accV = torch.empty(HW, dtype=torch.float32, device=dev)
+        accF = torch.empty((s.F, HW), dtype=torch.float32, device=dev)
+        for c0 in range(0, HW, chunk):
+            c1 = min(HW, c0 + chunk)
+            n = c1 - c0
+            base = ((t * HW + pix[c0:c1]) * s.spp).unsqueeze(1) + \
+                torch.arange(s.spp, dtype=torch.int64, device=dev).unsqueeze(0)
+            jx = _uniform(s.seed, 1, base)
+            jy = _uniform(s.seed, 2, base)
+            xs = (px[c0:c1].unsqueeze(1) + jx).reshape(-1)
+            ys = (py[c0:c1].unsqueeze(1) + jy).reshape(-1)
+            a = scene.shade(t, xs, ys)
+            un = _uniform(s.seed, 3, base).reshape(-1)
+            X = -torch.log1p(-un)                    # unit exponential = Gamma(k=1)
+            Es = (a["E"] * X).reshape(n, s.spp)
+            m = Es.mean(dim=1)
+            accE[c0:c1] = m
+            if s.spp > 1:
+                accV[c0:c1] = ((Es - m.unsqueeze(1)) ** 2).sum(dim=1) / (s.spp - 1)
+            else:
+                accV[c0:c1] = 0.0
+            for f, name in enumerate(chans):
+                accF[f, c0:c1] = a[name].reshape(n, s.spp).mean(dim=1)
+        E[ti] = accE.reshape(s.H, s.W)
+        V[ti] = accV.reshape(s.H, s.W)
+        feat[ti] = accF.reshape(s.F, s.H, s.W).to(fdt)
+    return dict(E=E, var=V, feat=feat, spec=s)
+
+
+def random_features_clip(W: int, H: int, T: int, F: int, seed: int, device="cpu",
+                         feat_dtype: str = "f32", scale: float = 0.5):
+    """Unstructured clip: i.i.d. uniform features in [-scale, scale] and
+    radiance from i.i.d. uniform values in [0.05, 1.05].  Used where every
+    window must have full rank (random features) or where structure would
+    hide an indexing mistake."""
+    n = T * H * W
+    idx = torch.arange(n * (F + 1), dtype=torch.int64, device=device)
+    u = _uniform(seed, 11, idx)
+    E = (0.05 + u[:n]).reshape(T, H, W)
+    feat = ((u[n:] * 2.0 - 1.0) * scale).reshape(T, F, H, W)
+    fdt = torch.float16 if feat_dtype == "f16" else torch.float32
+    return dict(E=E.contiguous(), var=torch.zeros_like(E), feat=feat.to(fdt).contiguous())
