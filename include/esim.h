@@ -1,0 +1,234 @@
+/*
+ * esim.h -- C ABI of the MI355X event simulator (libesim.so).
+ *
+ * The library turns noisy log-brightness frames plus per-pixel feature
+ * buffers into DVS events (x, y, t, polarity), following
+ * Tsuji, Yatagawa, Kubo, Morishima, "Event-based Camera Simulation using Monte
+ * Carlo Path Tracing with Adaptive Denoising", arXiv 2303.02608:
+ *
+ *   - Sec. 1.1, eq. (1): an event fires when the log-brightness change since
+ *     the pixel's last event reaches the contrast threshold C.
+ *   - Sec. 2.1, eqs. (2)-(5): weighted local regression (WLR) of the log
+ *     brightness y over a window of neighbours, with Gaussian feature weights.
+ *   - Sec. 2.2, eqs. (6)-(9) and Prop. 1: the residual of the last-event plane
+ *     translated to the new centre feature differs from the plane's own
+ *     residual by (beta^T (x^c - x_hat^c))^2; comparing that difference with
+ *     C^2 decides whether the regression has to be solved again.
+ *   - Sec. 3: the "WLR+ESIM" baseline (regress every pixel of every frame, then
+ *     eq. (1)) and the "ESIM" baseline (eq. (1) on the noisy frames).
+ *
+ * Conventions
+ *   - Every data pointer is DEVICE memory owned by the caller, except the
+ *     structs passed by pointer (host memory, read during the call only).
+ *   - Hot calls (log_brightness, threshold, regress, events, backward) are
+ *     asynchronous on the given stream (a hipStream_t; NULL = null stream),
+ *     allocate nothing, never synchronise, and may be captured in a hipGraph.
+ *     Argument validation is synchronous and happens before anything is
+ *     enqueued: on an error nothing has been launched.
+ *   - Pixel p of a clip is p = py * W + px; arrays are planar (SoA).
+ *   - A work item is an int64: bits [0,32) pixel, bits [32,44) clip index in the
+ *     plan, bits [44,63) frame (only used where a call says so).  The value -1
+ *     is a padding entry and is skipped.
+ *   - Entry points catch every exception; none crosses the ABI.
+ */
+#ifndef ESIM_H_
+#define ESIM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ESIM_MAX_F 12                 /* feature-buffer channels supported   */
+#define ESIM_MAX_D (ESIM_MAX_F + 2)   /* plus the two image coordinates      */
+
+typedef enum {
+  ESIM_OK = 0,
+  ESIM_E_INVAL = -1,        /* bad argument; nothing enqueued                  */
+  ESIM_E_HIP = -2,          /* HIP runtime or launch error                     */
+  ESIM_E_CAPACITY = -3,     /* a buffer is known to be too small               */
+  ESIM_E_UNSUPPORTED = -4   /* valid request outside what the build supports   */
+} esim_status;
+
+typedef enum { ESIM_F32 = 0, ESIM_F16 = 1 } esim_dtype;
+
+/* esim_events modes */
+typedef enum {
+  ESIM_INIT = 0,          /* store the frame's models as the reference state  */
+  ESIM_THRESHOLDED = 1,   /* the paper's method (Sec. 2.2)                     */
+  ESIM_EXHAUSTIVE = 2,    /* WLR+ESIM: eq. (1) on the regressed alpha           */
+  ESIM_RAW = 3            /* ESIM on the noisy frames: eq. (1) on y            */
+} esim_mode;
+
+/* Gram precision of the regression */
+typedef enum {
+  ESIM_GRAM_F64 = 0,      /* FP32 weights, FP64 Gram and FP64 Cholesky (default) */
+  ESIM_GRAM_F32C = 1      /* FP32 Gram with compensated sums, FP32 Cholesky,
+                             FP64 re-solve when kappa-hat > kappa_fp64          */
+} esim_precision;
+
+/* One clip.  y = log brightness [T][H][W] (see esim_log_brightness); feat =
+ * the F feature buffers [T][F][H][W] in feat_dtype.  The image coordinates
+ * are implicit features (px / r, py / r). */
+typedef struct {
+  int32_t W, H, T, F;
+  int32_t feat_dtype;
+  const float* y;
+  const void* feat;
+} esim_clip;
+
+/* Method parameters of one clip (Sec. 2.1 eq. 5; Sec. 1.1 eq. 1). */
+typedef struct {
+  int32_t r;               /* spatial window radius, >= 1                       */
+  int32_t tr;              /* temporal radius in frames, >= 0                    */
+  double C;                /* contrast threshold, > 0                           */
+  double h;                /* global bandwidth, > 0 (paper: 1)                  */
+  double b[ESIM_MAX_D];    /* per-dimension bandwidths, coordinates first, > 0  */
+  double ridge;            /* lambda >= 0 added to the beta block of the
+                              W-normalised Gram (the alpha row is untouched)    */
+  int32_t precision;       /* esim_precision                                    */
+  double kappa_fp64;       /* ESIM_GRAM_F32C: bound on kappa-hat               */
+} esim_params;
+
+/* Per-pixel reference state (Sec. 2.2: one regression model per pixel, kept
+ * until the pixel's next event).  alpha also holds L_ref of the exhaustive and
+ * raw baselines.  beta holds only the F buffer channels: the image-coordinate
+ * part of x^c - x_hat^c is zero for a pixel. */
+typedef struct {
+  float* alpha;            /* [H*W]                                              */
+  float* beta;             /* [F][H*W]                                           */
+  float* xref;             /* [F][H*W]  feature vector at the last event          */
+  int32_t* tref;           /* [H*W]     frame of the last event                    */
+} esim_state;
+
+/* Event sink.  Events are appended in (t, clip, py, px) order at *count; an
+ * event whose index reaches `capacity` is dropped but still counted, so a
+ * caller detects overflow by *count > capacity after synchronising.
+ * `clip` may be NULL.  Timestamps are frame indices (time = t * dt). */
+typedef struct {
+  int32_t* x;
+  int32_t* y;
+  int32_t* t;
+  int8_t* p;               /* polarity, +1 or -1                                */
+  int32_t* clip;
+  int64_t capacity;
+  int64_t* count;          /* device, running total                             */
+} esim_events_buf;
+
+typedef struct esim_plan_s* esim_plan;
+
+/* ---- set-up (not hot: these allocate and copy) ------------------------- */
+
+/* Build a plan over nclips clips (1 = the plain single-clip form; > 1 = the
+ * batched form).  Copies the clip descriptors, parameters and state pointers
+ * to the device and allocates the compaction workspace.  The plan keeps the
+ * pointers, not the data: the caller keeps y, feat and the states alive.
+ * Errors: E_INVAL (bad shape, F outside 1..ESIM_MAX_F, bad parameter),
+ * E_HIP (allocation or copy failed). */
+int esim_plan_create(const esim_clip* clips, const esim_params* params,
+                     const esim_state* states, int32_t nclips, esim_plan* out);
+int esim_plan_destroy(esim_plan plan);
+
+/* Total pixels over the plan's clips (sum of H*W): the length of dl, of dense
+ * regression outputs and of a work list, without padding. */
+int64_t esim_plan_pixels(esim_plan plan);
+/* Work-list capacity a threshold call may need: pixels plus per-clip padding. */
+int64_t esim_plan_worklist_capacity(esim_plan plan);
+/* First pixel of clip c in the concatenated pixel range. */
+int64_t esim_plan_pixel_offset(esim_plan plan, int32_t c);
+
+/* Schedule of the regression kernel (set by the autotuner, or by hand):
+ * lanes per regression item (2, 4 or 8) and persistent blocks per CU (1..64).
+ * Errors: E_UNSUPPORTED (lanes not compiled), E_INVAL. */
+int esim_plan_set_schedule(esim_plan plan, int32_t lanes, int32_t blocks_per_cu);
+
+/* ---- hot path ---------------------------------------------------------- */
+
+/* Log brightness (Sec. 1.1, L = log E): y[i] = log(E[i] + eps), elementwise, n values.
+ * Errors: E_INVAL (null pointer, n < 0, eps < 0). */
+int esim_log_brightness(const float* E, float* y, int64_t n, float eps, void* stream);
+
+/* Threshold and compaction (Sec. 2.2, Prop. 1, eqs. 8-9): for every pixel of every clip with
+ * 1 <= t < T, dL = sum_f beta_ref[f] (feat_t[f] - xref[f]) over the F buffer
+ * channels (computed in FP64 from the FP32 state), written to dl[pixel offset
+ * + p] (NaN for clips inactive at t); a pixel is flagged when dL^2 >= C^2.
+ * Flagged pixels are compacted into worklist as items (clip << 32 | p), in
+ * ascending (clip, p) order; each clip's segment is padded with -1 entries to
+ * a multiple of the plan's group size when the plan has more than one clip.
+ * count[0] = work-list length including padding, count[1] = flagged pixels.
+ * dl must hold esim_plan_pixels values, worklist
+ * esim_plan_worklist_capacity items, count two int32. */
+int esim_wlr_threshold(esim_plan plan, int32_t t, float* dl, int64_t* worklist,
+                       int32_t* count, void* stream);
+
+/* Weighted local regression (Sec. 2.1, eqs. 3-5): weighted local regression at
+ *   - the listed items (worklist != NULL; *count is read on the device and
+ *     clamped to n_out, so worklist must hold min(*count, n_out) entries;
+ *     item i's results go to index i), or
+ *   - every pixel of every clip active at t (worklist == NULL; the results of
+ *     pixel p of clip c go to index pixel_offset(c) + p).
+ * If t >= 0 every item is regressed at frame t; if t < 0 each item carries its
+ * frame in bits [44,63) (then every clip's feature array must stay below 4 GiB).
+ * Outputs (n_out = stride of beta, >= the largest index written):
+ *   alpha[i]          = fitted value at the centre (eq. 3's f(x^c)),
+ *   beta[d * n_out + i] (nullable) = gradient over the D = F + 2 features,
+ *                       coordinates first,
+ *   resid[i] (nullable) = R of eq. (4) at the minimiser,
+ *   kappa[i] (nullable) = kappa-hat: (max L_jj / min L_jj)^2 of the Cholesky
+ *                       factor of the W-normalised Gram, a lower bound of the
+ *                       2-norm condition number.
+ * Errors: E_INVAL (null outputs, n_out too small for dense mode),
+ * E_UNSUPPORTED (t < 0 with a clip of 4 GiB or more of features). */
+int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const int32_t* count,
+                     int64_t n_out, float* alpha, float* beta, float* resid, float* kappa,
+                     void* stream);
+
+/* Events and state updates (Sec. 1.1 eq. 1; Sec. 2.2; Sec. 3):
+ *   ESIM_INIT:        every pixel of every clip active at t: state <- (alpha,
+ *                     beta over the F buffer channels, feat_t, t) from dense
+ *                     regression outputs (index pixel_offset(c) + p, stride
+ *                     n_out).  No events.
+ *   ESIM_THRESHOLDED: for the work-list items of a threshold call at t: emit
+ *                     (px, py, t, sign dl) and replace the state with the
+ *                     item's regression (alpha[i], beta[.., i]), feat_t and t.
+ *   ESIM_EXHAUSTIVE:  every pixel: d = alpha - state.alpha (L_ref); if
+ *                     |d| >= C emit sign d and set L_ref <- alpha.  At t = 0
+ *                     (or for a fresh state) call ESIM_INIT first.
+ *   ESIM_RAW:         as EXHAUSTIVE with alpha replaced by y_t.  Pass
+ *                     alpha = NULL; mode INIT with alpha = NULL stores y_t.
+ * dl is the threshold call's output (THRESHOLDED and EXHAUSTIVE/RAW write the
+ * compared change to it when non-NULL in the latter two).
+ * Errors: E_INVAL (mode, missing buffers). */
+int esim_events(esim_plan plan, int32_t t, int32_t mode, const int64_t* worklist,
+                const int32_t* count, float* dl, const float* alpha, const float* beta,
+                int64_t n_out, esim_events_buf* ev, void* stream);
+
+/* Adjoint of alpha (eqs. 4-5 differentiated) at n regressions.  items
+ * carry their frame (bits [44,63)) and must be distinct; g_alpha[n] is the
+ * upstream gradient.  With A the W-normalised Gram plus ridge, theta its
+ * solution, v = A^{-1} e_0, s_i = v^T z_i, r_i = y_i - z_i^T theta:
+ *   g_y[t'][py'][px'] += sum_items g_alpha (w_i / W) s_i          (gather,
+ *                        deterministic: no atomics)
+ *   g_b[j]            += sum_items g_alpha sum_i (s_i r_i - lambda v^T E theta)
+ *                        / W * w_i u_ij^2 / (h^2 b_j^3),  j < F + 2.
+ * The window is recomputed, not stored.  Single-clip plans only; the clip's
+ * features must stay below 4 GiB.  scratch: esim_backward_scratch_bytes.
+ * Errors: E_INVAL, E_CAPACITY (scratch too small), E_UNSUPPORTED. */
+size_t esim_backward_scratch_bytes(esim_plan plan, int64_t n);
+int esim_wlr_backward(esim_plan plan, const int64_t* items, int64_t n, const float* g_alpha,
+                      float* g_y, double* g_b, void* scratch, size_t scratch_bytes, void* stream);
+
+/* ---- diagnostics ------------------------------------------------------- */
+const char* esim_status_string(int status);
+/* Message of the last failed call on this thread ("" if none). */
+const char* esim_last_error(void);
+/* Build information: the offload target and the compiled kernel variants. */
+const char* esim_build_info(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif  /* ESIM_H_ */

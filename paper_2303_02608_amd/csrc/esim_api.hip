@@ -1,0 +1,382 @@
+// Host side of libesim: plans, argument validation and launches.
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <exception>
+#include <string>
+#include <vector>
+
+#include "esim.h"
+#include "esim_compact.h"
+#include "esim_internal.h"
+
+struct esim_plan_s {
+  int nclips = 0;
+  int F = 0;
+  bool f16 = false;
+  std::vector<esim::ClipDev> host;
+  esim::ClipDev* dev = nullptr;
+  esim::Workspace ws{};
+  void* ws_mem = nullptr;
+  int64_t npix = 0;
+  int64_t nblk = 0;
+  int64_t wl_capacity = 0;
+  int64_t dense_groups[5] = {0, 0, 0, 0, 0};
+  int pad = 1;             // work-list padding per clip segment
+  int lanes = 4;           // lanes per regression item
+  int blocks_per_cu = 4;   // persistent grid: 256 CUs x this many blocks
+  uint64_t max_feat_bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const std::string& msg) {
+  g_last_error = msg;
+  return code;
+}
+
+int ok() {
+  g_last_error.clear();
+  return ESIM_OK;
+}
+
+int hip_check(hipError_t e, const char* where) {
+  if (e != hipSuccess) return fail(ESIM_E_HIP, std::string(where) + ": " + hipGetErrorString(e));
+  return ok();
+}
+
+constexpr int kMultiClipPad = 32;  // multiple of every wave-group size used
+
+}  // namespace
+
+extern "C" {
+
+const char* esim_status_string(int s) {
+  switch (s) {
+    case ESIM_OK: return "ok";
+    case ESIM_E_INVAL: return "invalid argument";
+    case ESIM_E_HIP: return "HIP error";
+    case ESIM_E_CAPACITY: return "capacity exceeded";
+    case ESIM_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* esim_last_error(void) { return g_last_error.c_str(); }
+
+const char* esim_build_info(void) {
+  return "libesim gfx950; regress: F=1..12 x lanes{2,4,8} x {f32,f16} features, FP64 Gram";
+}
+
+int esim_plan_create(const esim_clip* clips, const esim_params* params, const esim_state* states,
+                     int32_t nclips, esim_plan* out) {
+  try {
+    if (!out) return fail(ESIM_E_INVAL, "out is null");
+    *out = nullptr;
+    if (!clips || !params || nclips < 1 || nclips > 4096)
+      return fail(ESIM_E_INVAL, "clips/params null or nclips outside 1..4096");
+    auto* pl = new esim_plan_s();
+    pl->nclips = nclips;
+    pl->F = clips[0].F;
+    pl->f16 = clips[0].feat_dtype == ESIM_F16;
+    pl->pad = nclips > 1 ? kMultiClipPad : 1;
+    int64_t pix = 0, blk = 0, grp[5] = {0, 0, 0, 0, 0};
+    int64_t wl = 0;
+    for (int c = 0; c < nclips; ++c) {
+      const esim_clip& k = clips[c];
+      const esim_params& p = params[c];
+      char msg[256];
+      if (k.W < 1 || k.H < 1 || k.T < 1 || static_cast<int64_t>(k.W) * k.H >= (1ll << 31)) {
+        std::snprintf(msg, sizeof msg, "clip %d: bad shape W=%d H=%d T=%d", c, k.W, k.H, k.T);
+        delete pl;
+        return fail(ESIM_E_INVAL, msg);
+      }
+      if (k.F < 1 || k.F > ESIM_MAX_F) {
+        delete pl;
+        return fail(ESIM_E_UNSUPPORTED, "F outside 1..ESIM_MAX_F");
+      }
+      if (k.F != pl->F || (k.feat_dtype == ESIM_F16) != pl->f16 ||
+          (k.feat_dtype != ESIM_F32 && k.feat_dtype != ESIM_F16)) {
+        delete pl;
+        return fail(ESIM_E_UNSUPPORTED, "all clips of a plan share F and the feature dtype");
+      }
+      if (!k.y || !k.feat) {
+        delete pl;
+        return fail(ESIM_E_INVAL, "clip y/feat null");
+      }
+      if (p.r < 1 || p.r > 64 || p.tr < 0 || p.tr > 16 || !(p.C > 0) || !(p.h > 0) ||
+          !(p.ridge >= 0) || std::isinf(p.C)) {
+        std::snprintf(msg, sizeof msg, "clip %d: bad params r=%d tr=%d C=%g h=%g ridge=%g", c, p.r,
+                      p.tr, p.C, p.h, p.ridge);
+        delete pl;
+        return fail(ESIM_E_INVAL, msg);
+      }
+      if (p.precision != ESIM_GRAM_F64 && p.precision != ESIM_GRAM_F32C) {
+        delete pl;
+        return fail(ESIM_E_INVAL, "bad precision");
+      }
+      for (int d = 0; d < k.F + 2; ++d)
+        if (!(p.b[d] > 0) || std::isinf(p.b[d])) {
+          delete pl;
+          return fail(ESIM_E_INVAL, "bandwidths b must be positive and finite");
+        }
+      esim::ClipDev cd{};
+      cd.y = k.y;
+      cd.feat = k.feat;
+      if (states) {
+        cd.st_alpha = states[c].alpha;
+        cd.st_beta = states[c].beta;
+        cd.st_xref = states[c].xref;
+        cd.st_tref = states[c].tref;
+      }
+      cd.W = k.W;
+      cd.H = k.H;
+      cd.T = k.T;
+      cd.F = k.F;
+      cd.feat_f16 = k.feat_dtype == ESIM_F16;
+      cd.r = p.r;
+      cd.tr = p.tr;
+      cd.precision = p.precision;
+      cd.HW = static_cast<int64_t>(k.W) * k.H;
+      cd.pix_off = pix;
+      cd.blk_off = blk;
+      cd.nblk = (cd.HW + esim::kBlock - 1) / esim::kBlock;
+      const int Ls[5] = {1, 2, 4, 8, 16};
+      for (int q = 0; q < 5; ++q) {
+        cd.grp_off[q] = grp[q];
+        grp[q] += (cd.HW + (esim::kWave / Ls[q]) - 1) / (esim::kWave / Ls[q]);
+      }
+      cd.C = p.C;
+      cd.h = p.h;
+      cd.ridge = p.ridge;
+      cd.kappa_fp64 = p.kappa_fp64;
+      for (int d = 0; d < ESIM_MAX_D; ++d) {
+        const double bd = d < k.F + 2 ? p.b[d] : 1.0;
+        cd.c2[d] = 1.0 / (p.h * bd * p.h * bd);
+        cd.gbk[d] = 1.0 / (p.h * p.h * bd * bd * bd);
+      }
+      pix += cd.HW;
+      blk += cd.nblk;
+      wl += cd.HW + (pl->pad - 1);
+      const uint64_t fb = static_cast<uint64_t>(k.T) * k.F * cd.HW * (cd.feat_f16 ? 2u : 4u);
+      const uint64_t wb = static_cast<uint64_t>(2 * p.tr + 1) * k.F * cd.HW * (cd.feat_f16 ? 2u : 4u);
+      if (wb >= (1ull << 32) || static_cast<uint64_t>(2 * p.tr + 1) * cd.HW * 4u >= (1ull << 32)) {
+        delete pl;
+        return fail(ESIM_E_UNSUPPORTED, "the 2*tr+1 frames of a window must stay below 4 GiB");
+      }
+      pl->max_feat_bytes = std::max(pl->max_feat_bytes, fb);
+      pl->host.push_back(cd);
+    }
+    pl->npix = pix;
+    pl->nblk = blk;
+    pl->wl_capacity = wl;
+    for (int q = 0; q < 5; ++q) pl->dense_groups[q] = grp[q];
+
+    // device memory: descriptors + workspace
+    const size_t clip_bytes = sizeof(esim::ClipDev) * nclips;
+    auto align = [](size_t v) { return (v + 255) & ~static_cast<size_t>(255); };
+    size_t off = 0;
+    const size_t o_clips = off;
+    off = align(off + clip_bytes);
+    const size_t o_bcount = off;
+    off = align(off + sizeof(int32_t) * blk);
+    const size_t o_boff = off;
+    off = align(off + sizeof(int64_t) * blk);
+    const size_t o_flags = off;
+    off = align(off + sizeof(uint64_t) * blk * esim::kWavesPerBlock);
+    const size_t o_pol = off;
+    off = align(off + sizeof(uint64_t) * blk * esim::kWavesPerBlock);
+    const size_t o_seg = off;
+    off = align(off + sizeof(int64_t) * nclips);
+    const size_t o_pre = off;
+    off = align(off + sizeof(int64_t) * nclips);
+    const size_t o_misc = off;
+    off = align(off + sizeof(int64_t) * 4);
+    hipError_t e = hipMalloc(&pl->ws_mem, off);
+    if (e != hipSuccess) {
+      delete pl;
+      return hip_check(e, "hipMalloc(plan)");
+    }
+    char* m = static_cast<char*>(pl->ws_mem);
+    pl->dev = reinterpret_cast<esim::ClipDev*>(m + o_clips);
+    pl->ws.bcount = reinterpret_cast<int32_t*>(m + o_bcount);
+    pl->ws.boffset = reinterpret_cast<int64_t*>(m + o_boff);
+    pl->ws.flags = reinterpret_cast<uint64_t*>(m + o_flags);
+    pl->ws.pol = reinterpret_cast<uint64_t*>(m + o_pol);
+    pl->ws.seg_start = reinterpret_cast<int64_t*>(m + o_seg);
+    pl->ws.seg_prefix = reinterpret_cast<int64_t*>(m + o_pre);
+    pl->ws.misc = reinterpret_cast<int64_t*>(m + o_misc);
+    e = hipMemcpy(pl->dev, pl->host.data(), clip_bytes, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemset(m + o_bcount, 0, off - o_bcount);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+      hipFree(pl->ws_mem);
+      delete pl;
+      return hip_check(e, "plan upload");
+    }
+    *out = pl;
+    return ok();
+  } catch (const std::exception& ex) {
+    return fail(ESIM_E_HIP, ex.what());
+  } catch (...) {
+    return fail(ESIM_E_HIP, "unknown exception");
+  }
+}
+
+int esim_plan_destroy(esim_plan pl) {
+  if (!pl) return ok();
+  if (pl->ws_mem) hipFree(pl->ws_mem);
+  delete pl;
+  return ok();
+}
+
+int64_t esim_plan_pixels(esim_plan pl) { return pl ? pl->npix : -1; }
+int64_t esim_plan_worklist_capacity(esim_plan pl) { return pl ? pl->wl_capacity : -1; }
+int64_t esim_plan_pixel_offset(esim_plan pl, int32_t c) {
+  if (!pl || c < 0 || c >= pl->nclips) return -1;
+  return pl->host[c].pix_off;
+}
+
+int esim_log_brightness(const float* E, float* y, int64_t n, float eps, void* stream) {
+  try {
+    if (n < 0 || !(eps >= 0)) return fail(ESIM_E_INVAL, "n < 0 or eps < 0");
+    if (n == 0) return ok();
+    if (!E || !y) return fail(ESIM_E_INVAL, "null pointer");
+    return hip_check(esim::launch_log(E, y, n, eps, static_cast<hipStream_t>(stream)), "log_brightness");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+int esim_wlr_threshold(esim_plan pl, int32_t t, float* dl, int64_t* worklist, int32_t* count,
+                       void* stream) {
+  try {
+    if (!pl || !dl || !worklist || !count) return fail(ESIM_E_INVAL, "null argument");
+    if (t < 0) return fail(ESIM_E_INVAL, "t < 0");
+    for (const auto& c : pl->host)
+      if (!c.st_beta || !c.st_xref || !c.st_alpha || !c.st_tref)
+        return fail(ESIM_E_INVAL, "threshold needs the full state (alpha, beta, xref, tref)");
+    return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold,
+                                               dl, nullptr, pl->ws, pl->pad, worklist, count, nullptr,
+                                               static_cast<hipStream_t>(stream)),
+                     "threshold");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+int esim_wlr_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int32_t* count,
+                     int64_t n_out, float* alpha, float* beta, float* resid, float* kappa,
+                     void* stream) {
+  try {
+    if (!pl || !alpha) return fail(ESIM_E_INVAL, "null argument");
+    if (worklist && !count) return fail(ESIM_E_INVAL, "worklist without count");
+    if (!worklist && t < 0) return fail(ESIM_E_INVAL, "dense regression needs t >= 0");
+    if (!worklist && n_out < pl->npix) return fail(ESIM_E_INVAL, "n_out < plan pixels");
+    if (n_out < 0) return fail(ESIM_E_INVAL, "n_out < 0");
+    if (t < 0 && pl->max_feat_bytes >= (1ull << 32))
+      return fail(ESIM_E_UNSUPPORTED, "per-item frames need feature arrays below 4 GiB");
+    const int L = pl->lanes;
+    esim::RegressArgs a{};
+    a.clips = pl->dev;
+    a.nclips = pl->nclips;
+    a.t = t;
+    a.items = worklist;
+    a.count = count;
+    a.n_dense_groups = pl->dense_groups[esim::lanes_index(L)];
+    const int G = esim::kWave / L;
+    a.max_groups = worklist ? (std::max<int64_t>(n_out, 1) + G - 1) / G : a.n_dense_groups;
+    a.n_out = n_out;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.resid = resid;
+    a.kappa = kappa;
+    return hip_check(esim::launch_regress(a, pl->F, pl->f16, pl->host[0].precision, L, pl->blocks_per_cu,
+                                          static_cast<hipStream_t>(stream)),
+                     "regress");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+int esim_events(esim_plan pl, int32_t t, int32_t mode, const int64_t* worklist, const int32_t* count,
+                float* dl, const float* alpha, const float* beta, int64_t n_out, esim_events_buf* ev,
+                void* stream) {
+  try {
+    if (!pl) return fail(ESIM_E_INVAL, "null plan");
+    if (t < 0) return fail(ESIM_E_INVAL, "t < 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (const auto& c : pl->host)
+      if (!c.st_alpha) return fail(ESIM_E_INVAL, "state alpha is null");
+    if (mode == ESIM_INIT) {
+      if (alpha && n_out < pl->npix) return fail(ESIM_E_INVAL, "n_out < plan pixels");
+      return hip_check(esim::launch_init(pl->dev, pl->nclips, pl->nblk, t, alpha, beta, n_out, s), "init");
+    }
+    if (!ev || !ev->x || !ev->y || !ev->t || !ev->p || !ev->count || ev->capacity < 0)
+      return fail(ESIM_E_INVAL, "events buffer incomplete");
+    esim::EventsDev ed{ev->x, ev->y, ev->t, ev->p, ev->clip, ev->capacity, ev->count};
+    if (mode == ESIM_THRESHOLDED) {
+      if (!worklist || !count || !dl || !alpha || !beta)
+        return fail(ESIM_E_INVAL, "thresholded events need worklist, count, dl, alpha and beta");
+      if (n_out < 1) return fail(ESIM_E_INVAL, "n_out < 1");
+      for (const auto& c : pl->host)
+        if (!c.st_beta || !c.st_xref || !c.st_tref) return fail(ESIM_E_INVAL, "state incomplete");
+      return hip_check(esim::launch_list_events(pl->dev, pl->nclips, t, worklist, count, pl->wl_capacity,
+                                                dl, alpha, beta, n_out, pl->ws, ed, s),
+                       "events(thresholded)");
+    }
+    if (mode == ESIM_EXHAUSTIVE || mode == ESIM_RAW) {
+      if (mode == ESIM_EXHAUSTIVE && (!alpha || n_out < pl->npix))
+        return fail(ESIM_E_INVAL, "exhaustive events need dense alpha (n_out >= plan pixels)");
+      return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t,
+                                                 mode == ESIM_EXHAUSTIVE ? esim::kFlagExhaustive
+                                                                         : esim::kFlagRaw,
+                                                 dl, alpha, pl->ws, 1, nullptr, nullptr, &ed, s),
+                       "events");
+    }
+    return fail(ESIM_E_INVAL, "bad mode");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+size_t esim_backward_scratch_bytes(esim_plan pl, int64_t n) {
+  if (!pl || pl->nclips != 1 || n < 0) return 0;
+  return esim::backward_scratch_bytes(pl->host[0], n);
+}
+
+int esim_wlr_backward(esim_plan pl, const int64_t* items, int64_t n, const float* g_alpha, float* g_y,
+                      double* g_b, void* scratch, size_t scratch_bytes, void* stream) {
+  try {
+    if (!pl) return fail(ESIM_E_INVAL, "null plan");
+    if (pl->nclips != 1) return fail(ESIM_E_UNSUPPORTED, "backward supports single-clip plans");
+    if (n < 0) return fail(ESIM_E_INVAL, "n < 0");
+    if (n == 0) return ok();
+    if (!items || !g_alpha || !g_y || !g_b) return fail(ESIM_E_INVAL, "null argument");
+    if (pl->max_feat_bytes >= (1ull << 32))
+      return fail(ESIM_E_UNSUPPORTED, "backward needs a feature array below 4 GiB");
+    const size_t need = esim::backward_scratch_bytes(pl->host[0], n);
+    if (!scratch || scratch_bytes < need) return fail(ESIM_E_CAPACITY, "scratch too small");
+    esim::BackwardArgs a{pl->dev, &pl->host[0], items, n, g_alpha, g_y, g_b, scratch, scratch_bytes};
+    return hip_check(esim::launch_backward(a, static_cast<hipStream_t>(stream)), "backward");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+// Schedule override used by the autotuner: lanes per item (2, 4, 8) and
+// persistent blocks per CU.  Not part of the hot path.
+int esim_plan_set_schedule(esim_plan pl, int32_t lanes, int32_t blocks_per_cu) {
+  if (!pl) return fail(ESIM_E_INVAL, "null plan");
+  if (!(esim::regress_supported_lanes(pl->F) & lanes) || (lanes & (lanes - 1)))
+    return fail(ESIM_E_UNSUPPORTED, "lanes per item not compiled");
+  if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(ESIM_E_INVAL, "blocks_per_cu outside 1..64");
+  pl->lanes = lanes;
+  pl->blocks_per_cu = blocks_per_cu;
+  return ok();
+}
+
+}  // extern "C"

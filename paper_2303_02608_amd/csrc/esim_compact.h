@@ -1,0 +1,38 @@
+// Launchers of the threshold / compaction / event kernels.
+#pragma once
+
+#include "esim_internal.h"
+
+namespace esim {
+
+enum { kFlagThreshold = 0, kFlagExhaustive = 1, kFlagRaw = 2 };
+
+// Device view of an esim_events_buf.
+struct EventsDev {
+  int32_t* x;
+  int32_t* y;
+  int32_t* t;
+  int8_t* p;
+  int32_t* clip;
+  int64_t capacity;
+  int64_t* count;
+};
+
+hipError_t launch_log(const float* E, float* y, int64_t n, float eps, hipStream_t s);
+
+// flag -> scan -> scatter.  mode kFlagThreshold writes the work list and
+// count; the other modes append events to ev.
+hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
+                               float* dl, const float* alpha, const Workspace& ws, int pad,
+                               int64_t* worklist, int32_t* count, const EventsDev* ev,
+                               hipStream_t s);
+
+hipError_t launch_list_events(const ClipDev* clips, int nclips, int t, const int64_t* worklist,
+                              const int32_t* count, int64_t max_items, const float* dl,
+                              const float* alpha, const float* beta, int64_t n_out,
+                              const Workspace& ws, const EventsDev& ev, hipStream_t s);
+
+hipError_t launch_init(const ClipDev* clips, int nclips, int64_t nblk, int t, const float* alpha,
+                       const float* beta, int64_t n_out, hipStream_t s);
+
+}  // namespace esim

@@ -1,0 +1,309 @@
+// Threshold, compaction, event emission and state updates (HBM-bound).
+//
+//   log_kernel         Sec. 1.1: y = log(E + eps).
+//   flag_kernel        per pixel of a 256-pixel block:
+//                        threshold  - Prop. 1 / eqs. 8-9: dL = beta_ref^T (f_t -
+//                                     x_ref) over the F buffer channels (the
+//                                     image-coordinate part is zero for a
+//                                     pixel); flag when dL^2 >= C^2;
+//                        exhaustive - eq. 1 on the regressed alpha against L_ref;
+//                        raw        - eq. 1 on y against L_ref;
+//                      wave ballots of the flags and polarities, block counts.
+//   scan_kernel        one block: exclusive scan of the block counts per clip
+//                      (segments padded for multi-clip work lists), event base.
+//   scatter_kernel     rank = block offset + popcounts of the ballots below the
+//                      lane; writes the work list (threshold) or the events.
+//   list_events_kernel events of the work-list items and the state update
+//                      (Sec. 2.2: the model at the last event is kept until the
+//                      pixel's next event).
+//   init_kernel        state <- the models of frame t (no events).
+#include "esim_internal.h"
+#include "esim_compact.h"
+
+namespace esim {
+namespace {
+
+__device__ __forceinline__ float feat_at(const ClipDev& C, int t, int f, int64_t p) {
+  const int64_t i = (static_cast<int64_t>(t) * C.F + f) * C.HW + p;
+  if (C.feat_f16) {
+    const uint16_t h = static_cast<const uint16_t*>(C.feat)[i];
+    return static_cast<float>(__builtin_bit_cast(_Float16, h));
+  }
+  return static_cast<const float*>(C.feat)[i];
+}
+
+__device__ __forceinline__ int block_clip(const ClipDev* clips, int nclips, int64_t b) {
+  int cl = 0;
+  for (int c = 1; c < nclips; ++c)
+    if (clips[c].blk_off <= b) cl = c;
+  return cl;
+}
+
+__global__ void __launch_bounds__(256) log_kernel(const float* __restrict__ E, float* __restrict__ y,
+                                                  int64_t n, float eps) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
+    y[i] = logf(E[i] + eps);
+}
+
+__global__ void __launch_bounds__(kBlock)
+flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, float* __restrict__ dl,
+            const float* __restrict__ alpha, Workspace ws) {
+  __shared__ int wcount[kWavesPerBlock];
+  const int64_t b = blockIdx.x;
+  const int cl = block_clip(clips, nclips, b);
+  const ClipDev& C = clips[cl];
+  const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
+  const bool in = p < C.HW && t >= 0 && t < C.T;
+  bool flag = false, pos = false;
+  if (in) {
+    float val = __builtin_nanf("");
+    if (mode == kFlagThreshold) {
+      if (t >= 1) {
+        double d = 0.0;
+        for (int f = 0; f < C.F; ++f) {
+          const double bf = C.st_beta[f * C.HW + p];
+          const double xf = C.st_xref[f * C.HW + p];
+          d = fma(bf, static_cast<double>(feat_at(C, t, f, p)) - xf, d);
+        }
+        flag = d * d >= C.C * C.C;
+        pos = d > 0.0;
+        val = static_cast<float>(d);
+      }
+    } else {
+      const float L = mode == kFlagExhaustive ? alpha[C.pix_off + p]
+                                              : C.y[static_cast<int64_t>(t) * C.HW + p];
+      if (t == 0) {
+        C.st_alpha[p] = L;
+      } else {
+        const double d = static_cast<double>(L) - static_cast<double>(C.st_alpha[p]);
+        val = static_cast<float>(d);
+        if (fabs(d) >= C.C) {
+          flag = true;
+          pos = d > 0.0;
+          C.st_alpha[p] = L;
+        }
+      }
+    }
+    if (dl) dl[C.pix_off + p] = val;
+  }
+  const int w = threadIdx.x / kWave;
+  const uint64_t fm = __ballot(flag);
+  const uint64_t pm = __ballot(flag && pos);
+  if ((threadIdx.x & (kWave - 1)) == 0) {
+    ws.flags[b * kWavesPerBlock + w] = fm;
+    ws.pol[b * kWavesPerBlock + w] = pm;
+    wcount[w] = __popcll(fm);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int k = 0; k < kWavesPerBlock; ++k) s += wcount[k];
+    ws.bcount[b] = s;
+  }
+}
+
+// Exclusive scan of 1024 values held one per thread; returns the exclusive
+// prefix of this thread and writes the total to *total.
+__device__ int64_t block_scan_1024(int64_t v, int64_t* sh, int64_t* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int k = 0; k < 1024 / kWave; ++k) {
+      const int64_t s = sh[k];
+      sh[k] = run;
+      run += s;
+    }
+    sh[1024 / kWave] = run;
+  }
+  __syncthreads();
+  const int64_t ex = sh[w] + x - v;
+  *total = sh[1024 / kWave];
+  __syncthreads();
+  return ex;
+}
+
+__global__ void __launch_bounds__(1024)
+scan_kernel(const ClipDev* __restrict__ clips, int nclips, Workspace ws, int pad, int64_t* worklist,
+            int32_t* count, int64_t* ev_count) {
+  __shared__ int64_t sh[1024 / kWave + 1];
+  __shared__ int64_t base_sh;
+  if (threadIdx.x == 0) base_sh = ev_count ? *ev_count : 0;
+  __syncthreads();
+  const int64_t base = base_sh;
+  int64_t run = 0, real = 0;
+  for (int c = 0; c < nclips; ++c) {
+    const int64_t nb = clips[c].nblk, b0 = clips[c].blk_off;
+    if (threadIdx.x == 0) {
+      ws.seg_start[c] = run;
+      ws.seg_prefix[c] = real;
+    }
+    const int64_t chunk = (nb + 1023) / 1024;
+    const int64_t lo = b0 + min(nb, chunk * threadIdx.x);
+    const int64_t hi = b0 + min(nb, chunk * (threadIdx.x + 1));
+    int64_t s = 0;
+    for (int64_t b = lo; b < hi; ++b) s += ws.bcount[b];
+    int64_t tot;
+    int64_t off = block_scan_1024(s, sh, &tot) + run + base;
+    for (int64_t b = lo; b < hi; ++b) {
+      ws.boffset[b] = off;
+      off += ws.bcount[b];
+    }
+    run += tot;
+    real += tot;
+    if (pad > 1 && worklist) {
+      const int64_t npad = (pad - run % pad) % pad;
+      for (int64_t k = threadIdx.x; k < npad; k += blockDim.x) worklist[run + k] = -1;
+      run += npad;
+    }
+  }
+  if (threadIdx.x == 0) {
+    if (count) {
+      count[0] = static_cast<int32_t>(run);
+      count[1] = static_cast<int32_t>(real);
+    }
+    if (ev_count) *ev_count = base + real;
+    ws.misc[0] = base;
+  }
+}
+
+__global__ void __launch_bounds__(kBlock)
+scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, Workspace ws,
+               int64_t* __restrict__ worklist, EventsDev ev) {
+  const int64_t b = blockIdx.x;
+  const int cl = block_clip(clips, nclips, b);
+  const ClipDev& C = clips[cl];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const uint64_t m = ws.flags[b * kWavesPerBlock + w];
+  if (!((m >> lane) & 1ull)) return;
+  const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
+  int64_t off = ws.boffset[b];
+  for (int k = 0; k < w; ++k) off += __popcll(ws.flags[b * kWavesPerBlock + k]);
+  off += __popcll(m & ((1ull << lane) - 1ull));
+  if (mode == kFlagThreshold) {
+    worklist[off] = (static_cast<int64_t>(cl) << 32) | p;
+  } else if (off < ev.capacity) {
+    const bool pos = (ws.pol[b * kWavesPerBlock + w] >> lane) & 1ull;
+    ev.x[off] = static_cast<int32_t>(p % C.W);
+    ev.y[off] = static_cast<int32_t>(p / C.W);
+    ev.t[off] = t;
+    ev.p[off] = pos ? 1 : -1;
+    if (ev.clip) ev.clip[off] = cl;
+  }
+}
+
+__global__ void __launch_bounds__(256)
+list_events_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const int64_t* __restrict__ worklist,
+                   const int32_t* __restrict__ count, const float* __restrict__ dl,
+                   const float* __restrict__ alpha, const float* __restrict__ beta, int64_t n_out,
+                   int64_t max_items, Workspace ws, EventsDev ev) {
+  // the device count is clamped to the work-list capacity and output length
+  const int64_t n = max(static_cast<int64_t>(0),
+                        min(static_cast<int64_t>(count[0]), min(max_items, n_out)));
+  const int64_t base = *ev.count;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t it = worklist[i];
+    if (it < 0) continue;
+    const int cl = static_cast<int>((it >> 32) & 0xFFF);
+    if (cl >= nclips) continue;
+    const ClipDev& C = clips[cl];
+    const int64_t p = it & 0xFFFFFFFFll;
+    if (p >= C.HW || t >= C.T) continue;
+    const int64_t e = base + ws.seg_prefix[cl] + (i - ws.seg_start[cl]);
+    const float d = dl[C.pix_off + p];
+    if (e >= 0 && e < ev.capacity) {
+      ev.x[e] = static_cast<int32_t>(p % C.W);
+      ev.y[e] = static_cast<int32_t>(p / C.W);
+      ev.t[e] = t;
+      ev.p[e] = d > 0.0f ? 1 : -1;
+      if (ev.clip) ev.clip[e] = cl;
+    }
+    C.st_alpha[p] = alpha[i];
+    for (int f = 0; f < C.F; ++f) {
+      C.st_beta[f * C.HW + p] = beta[(2 + f) * n_out + i];
+      C.st_xref[f * C.HW + p] = feat_at(C, t, f, p);
+    }
+    C.st_tref[p] = t;
+  }
+}
+
+__global__ void advance_kernel(int64_t* ev_count, const int32_t* count) { *ev_count += count[1]; }
+
+__global__ void __launch_bounds__(kBlock)
+init_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const float* __restrict__ alpha,
+            const float* __restrict__ beta, int64_t n_out) {
+  const int64_t b = blockIdx.x;
+  const int cl = block_clip(clips, nclips, b);
+  const ClipDev& C = clips[cl];
+  const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
+  if (p >= C.HW || t < 0 || t >= C.T) return;
+  if (!alpha) {
+    C.st_alpha[p] = C.y[static_cast<int64_t>(t) * C.HW + p];
+    return;
+  }
+  const int64_t i = C.pix_off + p;
+  C.st_alpha[p] = alpha[i];
+  if (beta && C.st_beta)
+    for (int f = 0; f < C.F; ++f) C.st_beta[f * C.HW + p] = beta[(2 + f) * n_out + i];
+  if (C.st_xref)
+    for (int f = 0; f < C.F; ++f) C.st_xref[f * C.HW + p] = feat_at(C, t, f, p);
+  if (C.st_tref) C.st_tref[p] = t;
+}
+
+}  // namespace
+
+hipError_t launch_log(const float* E, float* y, int64_t n, float eps, hipStream_t s) {
+  int64_t blocks = (n + 255) / 256;
+  if (blocks > 65536) blocks = 65536;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(log_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, E, y, n, eps);
+  return hipGetLastError();
+}
+
+hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
+                               float* dl, const float* alpha, const Workspace& ws, int pad,
+                               int64_t* worklist, int32_t* count, const EventsDev* ev,
+                               hipStream_t s) {
+  hipLaunchKernelGGL(flag_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
+                     t, mode, dl, alpha, ws);
+  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, clips, nclips, ws, pad,
+                     mode == kFlagThreshold ? worklist : nullptr, count,
+                     mode == kFlagThreshold ? nullptr : ev->count);
+  EventsDev none{};
+  hipLaunchKernelGGL(scatter_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
+                     t, mode, ws, worklist, ev ? *ev : none);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_events(const ClipDev* clips, int nclips, int t, const int64_t* worklist,
+                              const int32_t* count, int64_t max_items, const float* dl,
+                              const float* alpha, const float* beta, int64_t n_out,
+                              const Workspace& ws, const EventsDev& ev, hipStream_t s) {
+  int64_t blocks = (max_items + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(list_events_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, clips,
+                     nclips, t, worklist, count, dl, alpha, beta, n_out, max_items, ws, ev);
+  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(1), 0, s, ev.count, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_init(const ClipDev* clips, int nclips, int64_t nblk, int t, const float* alpha,
+                       const float* beta, int64_t n_out, hipStream_t s) {
+  hipLaunchKernelGGL(init_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips, t,
+                     alpha, beta, n_out);
+  return hipGetLastError();
+}
+
+}  // namespace esim

@@ -1,0 +1,154 @@
+// Internal declarations of libesim (device descriptors, load helpers,
+// cross-lane reductions and the launchers each source file provides).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "esim.h"
+
+namespace esim {
+
+constexpr int kWave = 64;
+constexpr int kBlock = 256;                 // threads of flag/scatter blocks
+constexpr int kWavesPerBlock = kBlock / kWave;
+
+// Device descriptor of one clip of a plan.
+struct ClipDev {
+  const float* y;          // [T][H][W]
+  const void* feat;        // [T][F][H][W]
+  float* st_alpha;         // [HW]
+  float* st_beta;          // [F][HW]
+  float* st_xref;          // [F][HW]
+  int32_t* st_tref;        // [HW]
+  int32_t W, H, T, F;
+  int32_t feat_f16, r, tr, precision;
+  int64_t HW;
+  int64_t pix_off;         // first pixel in the concatenated pixel range
+  int64_t blk_off;         // first kBlock-pixel block of the flag/scatter grid
+  int64_t nblk;            // kBlock-pixel blocks of this clip
+  int64_t grp_off[5];      // first dense wave-group, per lanes-per-item 1,2,4,8,16
+  double C, h, ridge, kappa_fp64;
+  double c2[ESIM_MAX_D];   // 1 / (h b_j)^2
+  double gbk[ESIM_MAX_D];  // 1 / (h^2 b_j^3)
+};
+
+// Compaction workspace of a plan (device).
+struct Workspace {
+  int32_t* bcount;         // [nblk] flagged pixels per block
+  int64_t* boffset;        // [nblk] output offset of each block
+  uint64_t* flags;         // [nblk][kWavesPerBlock] flag ballots
+  uint64_t* pol;           // [nblk][kWavesPerBlock] positive-polarity ballots
+  int64_t* seg_start;      // [nclips] first work-list entry of each clip
+  int64_t* seg_prefix;     // [nclips] flagged pixels of the clips before
+  int64_t* misc;           // [4] ev_base of the last list-event call, ...
+};
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {
+  const uint32_t n = bytes >= 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(bytes);
+  // Raw (stride 0) buffer; the third dword selects 32-bit data for the gfx9 family.
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), static_cast<short>(0),
+                                           static_cast<int>(n), 0x00020000);
+}
+
+__device__ __forceinline__ float ld_f32(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+}
+
+__device__ __forceinline__ float ld_f16(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  const uint16_t h = __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0);
+  return static_cast<float>(__builtin_bit_cast(_Float16, h));
+}
+
+template <bool F16>
+__device__ __forceinline__ float ld_feat(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (F16) return ld_f16(r, voff, soff);
+  else return ld_f32(r, voff, soff);
+}
+
+// Lane-group sum with DPP.  After dpp_sum<L>(v) every lane of each aligned
+// group of L lanes (L in 1, 2, 4, 8, 16) holds the group's sum:
+//   quad_perm [1,0,3,2] and [2,3,0,1] give quad sums; row_half_mirror maps
+//   each quad onto the other quad of its half-row; row_mirror maps each
+//   half-row onto the other half of its row.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const uint64_t b = __builtin_bit_cast(uint64_t, v);
+  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xFFFFFFFFu), CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+  return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
+                                        static_cast<uint32_t>(lo));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                               0xF, 0xF, false));
+}
+
+template <int L>
+__device__ __forceinline__ double group_sum(double v) {
+  if constexpr (L >= 2) v += dpp_d<0xB1>(v);
+  if constexpr (L >= 4) v += dpp_d<0x4E>(v);
+  if constexpr (L >= 8) v += dpp_d<0x141>(v);
+  if constexpr (L >= 16) v += dpp_d<0x140>(v);
+  return v;
+}
+
+template <int L>
+__device__ __forceinline__ float group_sum(float v) {
+  if constexpr (L >= 2) v += dpp_f<0xB1>(v);
+  if constexpr (L >= 4) v += dpp_f<0x4E>(v);
+  if constexpr (L >= 8) v += dpp_f<0x141>(v);
+  if constexpr (L >= 16) v += dpp_f<0x140>(v);
+  return v;
+}
+
+__host__ __device__ constexpr int lanes_index(int L) {
+  return L == 1 ? 0 : L == 2 ? 1 : L == 4 ? 2 : L == 8 ? 3 : 4;
+}
+
+// Work item fields.
+__device__ __forceinline__ int item_clip(int64_t it) { return static_cast<int>((it >> 32) & 0xFFF); }
+__device__ __forceinline__ int64_t item_pixel(int64_t it) { return it & 0xFFFFFFFFll; }
+__device__ __forceinline__ int item_frame(int64_t it) { return static_cast<int>(it >> 44); }
+
+// ---- launchers (host) -----------------------------------------------------
+
+struct RegressArgs {
+  const ClipDev* clips;
+  int32_t nclips;
+  int32_t t;                // >= 0 uniform frame, < 0 frame from the item
+  const int64_t* items;     // nullptr = dense
+  const int32_t* count;
+  int64_t n_dense_groups;   // dense: wave-groups over all clips (for the chosen L)
+  int64_t max_groups;       // upper bound of groups (grid sizing)
+  int64_t n_out;
+  float* alpha;
+  float* beta;
+  float* resid;
+  float* kappa;
+};
+
+// Regression launcher: picks the kernel instance for (F, dtype, precision)
+// and the lanes-per-item L; returns hipSuccess or the launch error.
+hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
+                          int blocks_per_cu, hipStream_t s);
+int regress_supported_lanes(int F);
+
+struct BackwardArgs {
+  const ClipDev* clip;      // single clip (device)
+  const ClipDev* host_clip; // the same, host copy
+  const int64_t* items;
+  int64_t n;
+  const float* g_alpha;
+  float* g_y;
+  double* g_b;
+  void* scratch;
+  size_t scratch_bytes;
+};
+size_t backward_scratch_bytes(const ClipDev& hc, int64_t n);
+hipError_t launch_backward(const BackwardArgs& a, hipStream_t s);
+
+}  // namespace esim

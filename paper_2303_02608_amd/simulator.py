@@ -1,0 +1,94 @@
+"""Frame loop of the event simulator on the GPU.
+
+Three conversions of a clip (y = log brightness [T][H][W], feat [T][F][H][W]):
+
+* ``"thresholded"`` -- the paper's method (Sec. 2.2): regress every pixel at
+  frame 0, then per frame threshold (Prop. 1), regress only the flagged pixels
+  and emit their events.
+* ``"exhaustive"`` -- WLR+ESIM (Sec. 3): regress every pixel of every frame,
+  then eq. (1) on the regressed values.
+* ``"raw"`` -- ESIM on the noisy frames (Sec. 3): eq. (1) on y.
+
+Every step is a libesim call enqueued on one stream; the loop never
+synchronises, so it can be captured in a hipGraph and replayed.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import torch
+
+from . import binding as B
+
+MODES = ("thresholded", "exhaustive", "raw")
+
+
+class Simulator:
+    def __init__(self, y: torch.Tensor, feat: torch.Tensor, params: B.Params,
+                 capacity: Optional[int] = None, want_dl: bool = True):
+        T, F, H, W = feat.shape
+        self.T, self.F, self.H, self.W = T, F, H, W
+        self.HW = H * W
+        dev = feat.device
+        self.plan = B.Plan([y], [feat], [params])
+        self.state = self.plan.states[0]
+        self.dl = torch.empty(self.HW, dtype=torch.float32, device=dev)
+        self.worklist = torch.empty(self.plan.wl_capacity, dtype=torch.int64, device=dev)
+        self.count = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.alpha = torch.empty(self.HW, dtype=torch.float32, device=dev)
+        self.beta = torch.empty((F + 2, self.HW), dtype=torch.float32, device=dev)
+        if capacity is None:
+            capacity = min(T * self.HW, 1 << 26)
+        self.ev = B.Events(capacity, dev)
+        self.flagged = torch.zeros(T, dtype=torch.int32, device=dev)
+        self.graph = None
+        self.graph_mode = None
+
+    # -- one conversion, enqueued on the current stream --------------------
+    def enqueue(self, mode: str = "thresholded", record_flags: bool = True):
+        if mode not in MODES:
+            raise ValueError(mode)
+        p, n = self.plan, self.HW
+        self.ev.count.zero_()
+        if mode == "thresholded":
+            B.regress(p, 0, None, None, n, self.alpha, self.beta)
+            B.events(p, 0, B.INIT, None, alpha=self.alpha, beta=self.beta, n_out=n)
+            for t in range(1, self.T):
+                B.threshold(p, t, self.dl, self.worklist, self.count)
+                if record_flags:
+                    self.flagged[t:t + 1].copy_(self.count[1:2])
+                B.regress(p, t, self.worklist, self.count, n, self.alpha, self.beta)
+                B.events(p, t, B.THRESHOLDED, self.ev, worklist=self.worklist, count=self.count,
+                         dl=self.dl, alpha=self.alpha, beta=self.beta, n_out=n)
+        elif mode == "exhaustive":
+            for t in range(self.T):
+                B.regress(p, t, None, None, n, self.alpha, None)
+                B.events(p, t, B.EXHAUSTIVE, self.ev, dl=self.dl, alpha=self.alpha, n_out=n)
+        else:
+            for t in range(self.T):
+                B.events(p, t, B.RAW, self.ev, dl=self.dl)
+
+    def capture(self, mode: str = "thresholded"):
+        """Record one conversion into a hipGraph (torch.cuda.CUDAGraph)."""
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.enqueue(mode)          # warm-up outside the graph
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.enqueue(mode)
+        self.graph, self.graph_mode = g, mode
+        return g
+
+    def replay(self):
+        self.graph.replay()
+
+    def run(self, mode: str = "thresholded"):
+        self.enqueue(mode)
+        torch.cuda.synchronize()
+        return self.events()
+
+    def events(self):
+        return self.ev.host()

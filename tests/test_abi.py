@@ -1,0 +1,85 @@
+"""Host-only checks of the C ABI: the library loads, exports every symbol the
+header declares, and rejects bad arguments before touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2303_02608_amd import binding as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared():
+    src = open(os.path.join(ROOT, "include", "esim.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(esim_[a-z_0-9]+)\s*\(", src)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(B.LIB_PATH):
+        pytest.skip("libesim.so not built")
+    return B.load()
+
+
+def test_header_declares_the_four_calls():
+    names = _declared()
+    for n in ("esim_wlr_threshold", "esim_wlr_regress", "esim_events", "esim_wlr_backward"):
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(B.SIGNATURES), set(names) ^ set(B.SIGNATURES)
+
+
+def test_status_strings(lib):
+    assert lib.esim_status_string(0) == b"ok"
+    assert lib.esim_status_string(-1) == b"invalid argument"
+    assert b"gfx950" in lib.esim_build_info()
+
+
+def test_invalid_arguments_fail_before_any_launch(lib):
+    out = ctypes.c_void_p()
+    assert lib.esim_plan_create(None, None, None, 1, ctypes.byref(out)) == B.E_INVAL
+    assert b"null" in lib.esim_last_error()
+    assert lib.esim_plan_create(None, None, None, 1, None) == B.E_INVAL
+    assert lib.esim_log_brightness(None, None, -1, 1e-3, None) == B.E_INVAL
+    assert lib.esim_log_brightness(None, None, 10, 1e-3, None) == B.E_INVAL
+    assert lib.esim_log_brightness(None, None, 0, 1e-3, None) == B.OK
+    assert lib.esim_wlr_threshold(None, 1, None, None, None, None) == B.E_INVAL
+    assert lib.esim_wlr_regress(None, 0, None, None, 0, None, None, None, None, None) == B.E_INVAL
+    assert lib.esim_events(None, 0, 1, None, None, None, None, None, 0, None, None) == B.E_INVAL
+    assert lib.esim_wlr_backward(None, None, 1, None, None, None, None, 0, None) == B.E_INVAL
+    assert lib.esim_plan_pixels(None) == -1
+    assert lib.esim_plan_set_schedule(None, 4, 4) == B.E_INVAL
+
+
+def test_bad_shapes_and_params_are_rejected(lib):
+    """Plan validation runs on the host before any device allocation."""
+    F = 7
+    clip = B.esim_clip(64, 64, 4, F, B.F32, 1, 1)     # dummy non-null pointers
+    good = B.Params(r=5, tr=0, C=0.2)
+    out = ctypes.c_void_p()
+
+    def create(c, p):
+        return lib.esim_plan_create(ctypes.byref(c), ctypes.byref(p), None, 1, ctypes.byref(out))
+
+    bad_clip = B.esim_clip(0, 64, 4, F, B.F32, 1, 1)
+    assert create(bad_clip, good.struct(F)) == B.E_INVAL
+    assert create(B.esim_clip(64, 64, 4, 13, B.F32, 1, 1), good.struct(F)) == B.E_UNSUPPORTED
+    assert create(B.esim_clip(64, 64, 4, F, B.F32, None, 1), good.struct(F)) == B.E_INVAL
+    for p in (B.Params(r=0, tr=0, C=0.2), B.Params(r=5, tr=-1, C=0.2), B.Params(r=5, tr=0, C=0.0),
+              B.Params(r=5, tr=0, C=0.2, h=0.0), B.Params(r=5, tr=0, C=0.2, ridge=-1.0),
+              B.Params(r=5, tr=0, C=0.2, b=[1.0] * 8 + [0.0]),
+              B.Params(r=5, tr=0, C=0.2, precision=7)):
+        assert create(clip, p.struct(F)) == B.E_INVAL, vars(p)
+    # mixed F across clips of one plan
+    clips = (B.esim_clip * 2)(clip, B.esim_clip(64, 64, 4, 3, B.F32, 1, 1))
+    pars = (B.esim_params * 2)(good.struct(F), good.struct(F))
+    assert lib.esim_plan_create(clips, pars, None, 2, ctypes.byref(out)) == B.E_UNSUPPORTED
