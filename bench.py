@@ -1,0 +1,280 @@
+#!/usr/bin/env python3
+"""Benchmark of the event simulator on one MI355X.
+
+Workload: the DVS-scale clip -- 640x480 px, 120 frames at 1 ms, 8 spp
+exponential-noise radiance, 7 FP32 feature channels (normal, albedo, depth),
+window radius 7, temporal radius 1, C = 0.15 -- drawn by the seeded
+procedural generator directly in HBM.
+
+A step is one whole conversion of the clip: log brightness, then the paper's
+thresholded path (regress all pixels at frame 0; per frame threshold,
+compaction, regression of the flagged pixels, events).  The step is captured
+once in a hipGraph and replayed.  The exhaustive WLR+ESIM path is timed the
+same way on the same clip.  `value` is the thresholded path's pixel-frames/s
+(T*H*W per step); events/s are reported beside it.
+
+Roofline: the dominant kernel is the regression.  Its launches are bracketed
+with HIP events on the launch stream during an instrumented eager pass of the
+same conversion; achieved = algorithmic FLOPs (per regression
+|Omega| (P^2 + 4P + 4D) + P^3/3 + 2P^2, with the truncated window size) / the
+summed launch durations.  The CPU baseline is the FP64 oracle on a random
+sample of pixels of the same clip (all frames), on the host's cores.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "pixel-frames/s and events/s, thresholded vs exhaustive WLR, same MI355X"
+PEAK_ALU_TFLOPS = 78.6      # FP64 vector (= unpacked FP32) issue peak of MI355X
+PEAK_HBM_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def omega_sizes(x, y, t, W, H, T, r, tr):
+    """Truncated window size |Omega| of regressions centred at (x, y, t)."""
+    nx = np.minimum(x + r, W - 1) - np.maximum(x - r, 0) + 1
+    ny = np.minimum(y + r, H - 1) - np.maximum(y - r, 0) + 1
+    nt = np.minimum(t + tr, T - 1) - np.maximum(t - tr, 0) + 1
+    return nx.astype(np.int64) * ny * nt
+
+
+def regress_flops(omega, F):
+    D, P = F + 2, F + 3
+    return omega.astype(np.float64) * (P * P + 4 * P + 4 * D) + P ** 3 / 3.0 + 2 * P * P
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("esim_regress.hip", "esim_internal.h"):
+        with open(os.path.join(ROOT, "paper_2303_02608_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(launch_items):
+    """HBM bytes per launch of the regression kernel from the committed
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "regress_dvs_traffic.json")
+    try:
+        with open(path) as fh:
+            d = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--cpu-pixels", type=int, default=640 * 480,
+                    help="pixels of the clip the oracle simulates over all frames (random "
+                         "sample; default all)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-exhaustive", action="store_true")
+    ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU; the path shards by pixel rows across GPUs "
+              "only on paper (see DESIGN.md).  Run with --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2303_02608_amd import autotune
+    from paper_2303_02608_amd import binding as B
+    from paper_2303_02608_amd import synth
+    from paper_2303_02608_amd.simulator import Simulator
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    B.load()   # raises if libesim.so is missing: there is no fallback
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    cfg = synth.config_spec(1)
+    spec = cfg["spec"]
+    r, tr, C = cfg["r"], cfg["tr"], cfg["C"]
+    T, H, W, F = spec.T, spec.H, spec.W, spec.F
+    t0 = time.time()
+    clip = synth.make_clip(spec, device=dev)
+    torch.cuda.synchronize()
+    log(f"generated {W}x{H}x{T} spp={spec.spp} F={F} in {time.time() - t0:.1f}s")
+    E, feat = clip["E"].contiguous(), clip["feat"].contiguous()
+    y = torch.empty_like(E)
+    params = B.Params(r=r, tr=tr, C=C)
+    sim = Simulator(y, feat, params)
+    pf = T * H * W
+    B.log_brightness(E, out=y)
+    t0 = time.time()
+    sched = autotune.tune(sim.plan, verbose=False)
+    log(f"autotuned schedule (lanes dense, lanes list, blocks/CU) = {sched} in {time.time() - t0:.1f}s")
+
+    def step(mode):
+        B.log_brightness(E, out=y)
+        sim.enqueue(mode)
+
+    def timed(mode):
+        if not args.eager:
+            s = torch.cuda.Stream()
+            s.wait_stream(torch.cuda.current_stream())
+            with torch.cuda.stream(s):
+                step(mode)
+            torch.cuda.current_stream().wait_stream(s)
+            torch.cuda.synchronize()
+            g = torch.cuda.CUDAGraph()
+            with torch.cuda.graph(g):
+                step(mode)
+            run = g.replay
+        else:
+            run = lambda: step(mode)
+        for _ in range(args.warmup):
+            run()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        w0 = time.perf_counter()
+        e0.record()
+        for _ in range(args.steps):
+            run()
+        e1.record()
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - w0) / args.steps * 1e3
+        ms = e0.elapsed_time(e1) / args.steps
+        ev = sim.events()
+        return ms, wall, ev
+
+    ms_thr, wall_thr, ev_thr = timed("thresholded")
+    flagged = sim.flagged.cpu().numpy()[1:]
+    phi = float(flagged.sum()) / ((T - 1) * H * W)
+    log(f"thresholded: {ms_thr:.3f} ms/step (wall {wall_thr:.3f}), events {ev_thr['count']}, "
+        f"flagged fraction {phi:.4f} (per-frame min {flagged.min() / (H * W):.4f} "
+        f"max {flagged.max() / (H * W):.4f})")
+    exh = None
+    if not args.no_exhaustive:
+        ms_exh, wall_exh, ev_exh = timed("exhaustive")
+        log(f"exhaustive: {ms_exh:.3f} ms/step (wall {wall_exh:.3f}), events {ev_exh['count']}")
+        exh = dict(value=pf / (ms_exh * 1e-3), unit="pixel-frames/s", ms_per_step=ms_exh,
+                   events_per_s=ev_exh["count"] / (ms_exh * 1e-3), events=ev_exh["count"])
+
+    # ---- roofline of the regression kernel: instrumented eager pass --------
+    stream = torch.cuda.current_stream()
+    marks = []
+    orig = B.regress
+
+    def timed_regress(*a, **k):
+        s0, s1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        orig(*a, **k)
+        s1.record(stream)
+        marks.append((s0, s1))
+
+    B.regress = timed_regress
+    try:
+        B.log_brightness(E, out=y)
+        sim.enqueue("thresholded")
+        torch.cuda.synchronize()
+    finally:
+        B.regress = orig
+    durs = np.array([a.elapsed_time(b) for a, b in marks])     # ms per launch
+    ev = sim.events()
+    omega = np.concatenate([
+        omega_sizes(np.arange(H * W) % W, np.arange(H * W) // W, np.zeros(H * W, np.int64),
+                    W, H, T, r, tr),
+        omega_sizes(ev["x"].astype(np.int64), ev["y"].astype(np.int64), ev["t"].astype(np.int64),
+                    W, H, T, r, tr)])
+    flops = regress_flops(omega, F).sum()
+    achieved = flops / (durs.sum() * 1e-3) / 1e12
+    n_launch = len(durs)
+    traffic = traffic_from_profile(None)
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS,
+            "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4),
+            "traffic": traffic, "kernel": "regress_kernel<F=7,L=4,f32>",
+            "launches": n_launch, "avg_launch_ms": round(float(durs.mean()), 4),
+            "flop_per_launch": float(flops / n_launch),
+            "regress_share_of_step": round(float(durs.sum()) / ms_thr, 3)}
+    log(f"regress: {n_launch} launches, {durs.sum():.3f} ms total, {achieved:.2f} TFLOP/s")
+
+    # ---- dense (exhaustive) regression roofline, same method ---------------
+    if exh is not None:
+        marks.clear()
+        B.regress = timed_regress
+        try:
+            sim.enqueue("exhaustive")
+            torch.cuda.synchronize()
+        finally:
+            B.regress = orig
+        d2 = np.array([a.elapsed_time(b) for a, b in marks])
+        tt = np.repeat(np.arange(T, dtype=np.int64), H * W)
+        om = omega_sizes(np.tile(np.arange(H * W) % W, T), np.tile(np.arange(H * W) // W, T), tt,
+                         W, H, T, r, tr)
+        exh["regress_tflops"] = round(regress_flops(om, F).sum() / (d2.sum() * 1e-3) / 1e12, 3)
+        exh["regress_frac"] = round(exh["regress_tflops"] / PEAK_ALU_TFLOPS, 4)
+
+    # ---- CPU baseline: the FP64 oracle on a random pixel sample -----------
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+        rng = np.random.default_rng(1234)
+        pix = np.sort(rng.choice(H * W, size=min(args.cpu_pixels, H * W), replace=False))
+        En = E.cpu().numpy()
+        fn = feat.cpu().numpy()
+        oc = oracle.Clip(oracle.log_brightness(En), fn)
+        c0 = time.perf_counter()
+        out = oracle.run(oc, oracle.Params(r, tr, C), oracle.THRESHOLDED, pixels=pix,
+                         nthreads=nthreads)
+        secs = time.perf_counter() - c0
+        cpu = {"value": round(pix.size * T / secs, 1), "unit": "pixel-frames/s", "cores": nthreads,
+               "kind": "oracle",
+               "sample": f"{pix.size} random pixels x {T} frames of the same clip, thresholded "
+                         f"path, FP64, {secs:.1f}s; events/s {out['count'] / secs:.1f}"}
+        log(f"oracle: {secs:.1f}s for {pix.size} px x {T} frames ({nthreads} threads)")
+
+    res = {
+        "metric": METRIC,
+        "value": round(pf / (ms_thr * 1e-3), 1),
+        "unit": "pixel-frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_thr, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"DVS {W}x{H}x{T}, {spec.spp} spp, F={F} f32, r={r}, tr={tr}, "
+                               f"C={C}, thresholded path",
+                   "W": W, "H": H, "T": T, "spp": spec.spp, "F": F, "r": r, "tr": tr, "C": C,
+                   "graph": not args.eager, "schedule": list(sched)},
+        "events_per_s": round(ev_thr["count"] / (ms_thr * 1e-3), 1),
+        "events": ev_thr["count"],
+        "flagged_fraction": round(phi, 5),
+        "exhaustive": exh,
+        "speedup_vs_exhaustive": round(exh["ms_per_step"] / ms_thr, 3) if exh else None,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

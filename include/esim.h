@@ -139,10 +139,13 @@ int64_t esim_plan_worklist_capacity(esim_plan plan);
 /* First pixel of clip c in the concatenated pixel range. */
 int64_t esim_plan_pixel_offset(esim_plan plan, int32_t c);
 
-/* Schedule of the regression kernel (set by the autotuner, or by hand):
- * lanes per regression item (2, 4 or 8) and persistent blocks per CU (1..64).
+/* Schedule of the regression kernel (set by the autotuner, or by hand): the
+ * lanes that share one regression item in dense launches and in work-list
+ * launches (2, 4, 8 or 16; more lanes = more, shorter wave tasks for sparse
+ * lists) and the persistent blocks per CU (1..64).  Defaults 4, 16, 4.
  * Errors: E_UNSUPPORTED (lanes not compiled), E_INVAL. */
-int esim_plan_set_schedule(esim_plan plan, int32_t lanes, int32_t blocks_per_cu);
+int esim_plan_set_schedule(esim_plan plan, int32_t lanes_dense, int32_t lanes_list,
+                           int32_t blocks_per_cu);
 
 /* ---- hot path ---------------------------------------------------------- */
 
@@ -177,8 +180,10 @@ int esim_wlr_threshold(esim_plan plan, int32_t t, float* dl, int64_t* worklist,
  *                       coordinates first,
  *   resid[i] (nullable) = R of eq. (4) at the minimiser,
  *   kappa[i] (nullable) = kappa-hat: (max L_jj / min L_jj)^2 of the Cholesky
- *                       factor of the W-normalised Gram, a lower bound of the
- *                       2-norm condition number.
+ *                       factor of the W-normalised Gram in bandwidth-scaled
+ *                       regressors u_j / (h b_j), a lower bound of that
+ *                       system's 2-norm condition number (the unscaled system
+ *                       when all bandwidths are 1).
  * Errors: E_INVAL (null outputs, n_out too small for dense mode),
  * E_UNSUPPORTED (t < 0 with a clip of 4 GiB or more of features). */
 int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const int32_t* count,

@@ -64,7 +64,7 @@ SIGNATURES = {
     "esim_plan_pixels": (_i64, [_vp]),
     "esim_plan_worklist_capacity": (_i64, [_vp]),
     "esim_plan_pixel_offset": (_i64, [_vp, _i32]),
-    "esim_plan_set_schedule": (_i32, [_vp, _i32, _i32]),
+    "esim_plan_set_schedule": (_i32, [_vp, _i32, _i32, _i32]),
     "esim_log_brightness": (_i32, [_vp, _vp, _i64, _f32, _vp]),
     "esim_wlr_threshold": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "esim_wlr_regress": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
@@ -181,6 +181,7 @@ class Plan:
         self.offsets = [lib.esim_plan_pixel_offset(h, i) for i in range(n)]
         self.F = feats[0].shape[1]
         self.D = self.F + 2
+        self.schedule = (4, 16, 4)
 
     def __del__(self):
         h = getattr(self, "h", None)
@@ -188,8 +189,10 @@ class Plan:
             _lib.esim_plan_destroy(h)
             self.h = None
 
-    def set_schedule(self, lanes: int, blocks_per_cu: int):
-        _check(load().esim_plan_set_schedule(self.h, lanes, blocks_per_cu), "set_schedule")
+    def set_schedule(self, lanes_dense: int, lanes_list: int, blocks_per_cu: int):
+        _check(load().esim_plan_set_schedule(self.h, lanes_dense, lanes_list, blocks_per_cu),
+               "set_schedule")
+        self.schedule = (lanes_dense, lanes_list, blocks_per_cu)
 
 
 class Events:

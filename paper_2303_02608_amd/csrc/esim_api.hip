@@ -24,7 +24,8 @@ struct esim_plan_s {
   int64_t wl_capacity = 0;
   int64_t dense_groups[5] = {0, 0, 0, 0, 0};
   int pad = 1;             // work-list padding per clip segment
-  int lanes = 4;           // lanes per regression item
+  int lanes_dense = 4;     // lanes per regression item, dense launches
+  int lanes_list = 16;     // lanes per regression item, work-list launches
   int blocks_per_cu = 4;   // persistent grid: 256 CUs x this many blocks
   uint64_t max_feat_bytes = 0;
 };
@@ -68,7 +69,7 @@ const char* esim_status_string(int s) {
 const char* esim_last_error(void) { return g_last_error.c_str(); }
 
 const char* esim_build_info(void) {
-  return "libesim gfx950; regress: F=1..12 x lanes{2,4,8} x {f32,f16} features, FP64 Gram";
+  return "libesim gfx950; regress: F=1..12 x lanes{2,4,8,16} x {f32,f16} features, FP64 Gram";
 }
 
 int esim_plan_create(const esim_clip* clips, const esim_params* params, const esim_state* states,
@@ -156,6 +157,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       for (int d = 0; d < ESIM_MAX_D; ++d) {
         const double bd = d < k.F + 2 ? p.b[d] : 1.0;
         cd.c2[d] = 1.0 / (p.h * bd * p.h * bd);
+        cd.sf[d] = 1.0 / (p.h * bd);
         cd.gbk[d] = 1.0 / (p.h * p.h * bd * bd * bd);
       }
       pix += cd.HW;
@@ -279,7 +281,7 @@ int esim_wlr_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int
     if (n_out < 0) return fail(ESIM_E_INVAL, "n_out < 0");
     if (t < 0 && pl->max_feat_bytes >= (1ull << 32))
       return fail(ESIM_E_UNSUPPORTED, "per-item frames need feature arrays below 4 GiB");
-    const int L = pl->lanes;
+    const int L = worklist ? pl->lanes_list : pl->lanes_dense;
     esim::RegressArgs a{};
     a.clips = pl->dev;
     a.nclips = pl->nclips;
@@ -367,14 +369,18 @@ int esim_wlr_backward(esim_plan pl, const int64_t* items, int64_t n, const float
   }
 }
 
-// Schedule override used by the autotuner: lanes per item (2, 4, 8) and
-// persistent blocks per CU.  Not part of the hot path.
-int esim_plan_set_schedule(esim_plan pl, int32_t lanes, int32_t blocks_per_cu) {
+// Schedule override used by the autotuner: lanes per item for dense and for
+// work-list launches (2, 4, 8, 16) and persistent blocks per CU.  Not part of
+// the hot path.
+int esim_plan_set_schedule(esim_plan pl, int32_t lanes_dense, int32_t lanes_list,
+                           int32_t blocks_per_cu) {
   if (!pl) return fail(ESIM_E_INVAL, "null plan");
-  if (!(esim::regress_supported_lanes(pl->F) & lanes) || (lanes & (lanes - 1)))
-    return fail(ESIM_E_UNSUPPORTED, "lanes per item not compiled");
+  const int sup = esim::regress_supported_lanes(pl->F);
+  for (int L : {lanes_dense, lanes_list})
+    if (L < 1 || (L & (L - 1)) || !(sup & L)) return fail(ESIM_E_UNSUPPORTED, "lanes per item not compiled");
   if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(ESIM_E_INVAL, "blocks_per_cu outside 1..64");
-  pl->lanes = lanes;
+  pl->lanes_dense = lanes_dense;
+  pl->lanes_list = lanes_list;
   pl->blocks_per_cu = blocks_per_cu;
   return ok();
 }

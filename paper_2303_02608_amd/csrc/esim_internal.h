@@ -31,6 +31,7 @@ struct ClipDev {
   int64_t grp_off[5];      // first dense wave-group, per lanes-per-item 1,2,4,8,16
   double C, h, ridge, kappa_fp64;
   double c2[ESIM_MAX_D];   // 1 / (h b_j)^2
+  double sf[ESIM_MAX_D];   // 1 / (h b_j)
   double gbk[ESIM_MAX_D];  // 1 / (h^2 b_j^3)
 };
 
@@ -72,19 +73,21 @@ __device__ __forceinline__ float ld_feat(__amdgpu_buffer_rsrc_t r, uint32_t voff
 //   quad_perm [1,0,3,2] and [2,3,0,1] give quad sums; row_half_mirror maps
 //   each quad onto the other quad of its half-row; row_mirror maps each
 //   half-row onto the other half of its row.
+// All lanes take part and every source lane of these controls lies inside the
+// row, so no lane keeps an "old" value (bound_ctrl set, full masks).
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
   const uint64_t b = __builtin_bit_cast(uint64_t, v);
-  const int lo = __builtin_amdgcn_update_dpp(0, static_cast<int>(b & 0xFFFFFFFFu), CTRL, 0xF, 0xF, false);
-  const int hi = __builtin_amdgcn_update_dpp(0, static_cast<int>(b >> 32), CTRL, 0xF, 0xF, false);
+  const int lo = __builtin_amdgcn_mov_dpp(static_cast<int>(b & 0xFFFFFFFFu), CTRL, 0xF, 0xF, true);
+  const int hi = __builtin_amdgcn_mov_dpp(static_cast<int>(b >> 32), CTRL, 0xF, 0xF, true);
   return __builtin_bit_cast(double, (static_cast<uint64_t>(static_cast<uint32_t>(hi)) << 32) |
                                         static_cast<uint32_t>(lo));
 }
 
 template <int CTRL>
 __device__ __forceinline__ float dpp_f(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
-                                                               0xF, 0xF, false));
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF,
+                                                            0xF, true));
 }
 
 template <int L>

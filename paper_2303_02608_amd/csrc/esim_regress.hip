@@ -14,8 +14,8 @@
 // channel stride in the SGPR offset), coalesced over the L adjacent columns of
 // an item and over the G adjacent items of a dense wave.
 //
-// Precision.  The weight exponent is summed in FP64 from exact FP64
-// differences and exponentiated with the FP32 hardware exp2 (about 1e-7
+// Precision.  The weight exponent is summed in FP64 from FP64 differences of
+// the FP32 inputs and exponentiated with the FP32 hardware exp2 (about 1e-7
 // relative).  Gram, right-hand side and Cholesky are FP64: without packed FP32
 // (disabled in this build) an FP64 FMA issues at the same rate as an FP32 one
 // on CDNA4, and the windows are ill-conditioned (kappa up to ~1e6 with a
@@ -113,15 +113,20 @@ regress_kernel(RegressArgs a) {
     const uint32_t vcen_f = (static_cast<uint32_t>(fc) * F * HW + static_cast<uint32_t>(pix)) * ES;
     const uint32_t vcen_y = (static_cast<uint32_t>(fc) * HW + static_cast<uint32_t>(pix)) * 4u;
 
-    double xc[F];
+    // Regressors are kept in bandwidth-scaled units v_j = u_j / (h b_j): the
+    // weight exponent is then sum_j v_j^2, and the fit in v is the fit in u
+    // with beta_j = theta_j / (h b_j) and the ridge scaled to lambda / (h b_j)^2.
+    double sf[D], xcs[F];
 #pragma unroll
-    for (int f = 0; f < F; ++f) xc[f] = static_cast<double>(ld_feat<F16>(rf, vcen_f, f * HW * ES));
-    double c2[D];
+    for (int d = 0; d < D; ++d) sf[d] = C.sf[d];
 #pragma unroll
-    for (int d = 0; d < D; ++d) c2[d] = C.c2[d];
+    for (int f = 0; f < F; ++f)
+      xcs[f] = static_cast<double>(ld_feat<F16>(rf, vcen_f, f * HW * ES)) * sf[2 + f];
 
     const double rinv = 1.0 / r;
+    const double vx_step = rinv * sf[0], vy_step = rinv * sf[1];
     const int dt_lo = max(-tr, -tt), dt_hi = min(tr, T - 1 - tt);
+    const int nrows = (dt_hi - dt_lo + 1) * (2 * r + 1);
 
     // accumulators (see the header comment for the x-folding)
     double SW = 0, A0y = 0, g0 = 0, A0f[F];
@@ -137,97 +142,98 @@ regress_kernel(RegressArgs a) {
       const int dx = -r + j + k * L;
       const int col = px + dx;
       const bool col_ok = active && dx <= r && col >= 0 && col < W;
-      const double ux = dx * rinv;
-      const double kx = kHalfLog2e * c2[0] * ux * ux;
+      const double vx = dx * vx_step;
+      const double kx = kHalfLog2e * vx * vx;
       double qW = 0, qY = 0, qG = 0, qF[F];
 #pragma unroll
       for (int f = 0; f < F; ++f) qF[f] = 0.0;
-      // The rows (dt, dy) of this column form one flat loop, software
-      // pipelined: the loads of the next row are issued before the current
-      // row is accumulated.  Rows outside the image read the (valid) centre
-      // pixel and get weight 0.
-      const int nrows = (dt_hi - dt_lo + 1) * (2 * r + 1);
-      int dt = dt_lo, dy = -r;
-      auto row_offsets = [&](int dt_, int dy_, uint32_t& vf, uint32_t& vy) -> bool {
-        const int row = py + dy_;
-        const bool ok = col_ok && row >= 0 && row < H;
-        const uint32_t fr = static_cast<uint32_t>(fc + dt_);
+
+      // The rows (dt, dy) of this column are streamed through two register
+      // buffers: the loads of one row are in flight while the other row is
+      // accumulated.  Rows outside the image (or past the last row) read the
+      // valid centre pixel and get weight 0.
+      int ldt = dt_lo, ldy = -r;   // next row to load
+      auto load_row = [&](float& yv, float (&fv)[F]) -> bool {
+        const int row = py + ldy;
+        // bitwise tests and selects keep the row addressing branch-free
+        const bool ok = (ldt <= dt_hi) & col_ok & (row >= 0) & (row < H);
         const uint32_t pofs = static_cast<uint32_t>(row * W + col);
-        vf = ok ? (fr * F * HW + pofs) * ES : vcen_f;
-        vy = ok ? (fr * HW + pofs) * 4u : vcen_y;
+        const uint32_t fr = static_cast<uint32_t>(fc + ldt);
+        const uint32_t vf_row = (fr * F * HW + pofs) * ES;
+        const uint32_t vy_row = (fr * HW + pofs) * 4u;
+        const uint32_t vf = ok ? vf_row : vcen_f;
+        const uint32_t vy = ok ? vy_row : vcen_y;
+        yv = ld_f32(ry, vy, 0);
+#pragma unroll
+        for (int f = 0; f < F; ++f) fv[f] = ld_feat<F16>(rf, vf, f * HW * ES);
+        if (++ldy > r) {
+          ldy = -r;
+          ++ldt;
+        }
         return ok;
       };
-      uint32_t vf, vy;
-      bool nok = row_offsets(dt, dy, vf, vy);
-      float ny = ld_f32(ry, vy, 0);
-      float nf[F];
-#pragma unroll
-      for (int f = 0; f < F; ++f) nf[f] = ld_feat<F16>(rf, vf, f * HW * ES);
-#pragma unroll 1
-      for (int q = 0; q < nrows; ++q) {
-        const bool ok = nok;
-        const float cy = ny;
-        float cf[F];
-#pragma unroll
-        for (int f = 0; f < F; ++f) cf[f] = nf[f];
-        const int cdy = dy;
-        if (++dy > r) {
-          dy = -r;
-          ++dt;
-        }
-        // next row (past the last row this re-reads a valid address)
-        nok = q + 1 < nrows ? row_offsets(dt, dy, vf, vy) : row_offsets(dt_lo, -r, vf, vy);
-        ny = ld_f32(ry, vy, 0);
-#pragma unroll
-        for (int f = 0; f < F; ++f) nf[f] = ld_feat<F16>(rf, vf, f * HW * ES);
-
-        const double yv = static_cast<double>(cy);
-        double u[F];
-        double s = 0.0;
+      int cdy = -r;                // dy of the row being accumulated
+      auto accumulate = [&](float yv, const float (&fv)[F], bool ok) {
+        const double vy = static_cast<double>(cdy) * vy_step;
+        if (++cdy > r) cdy = -r;
+        double v[F];
+        double s0 = 0.0, s1 = 0.0;
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-          u[f] = static_cast<double>(cf[f]) - xc[f];
-          s = fma(u[f] * c2[2 + f], u[f], s);
+          v[f] = fma(static_cast<double>(fv[f]), sf[2 + f], -xcs[f]);
+          if (f & 1) s1 = fma(v[f], v[f], s1);
+          else s0 = fma(v[f], v[f], s0);
         }
-        const double dyd = static_cast<double>(cdy);
-        const double uy = dyd * rinv;
-        const double arg = fma(s, kHalfLog2e, fma(kHalfLog2e * c2[1] * rinv * rinv, dyd * dyd, kx));
-        const float w32 = ok ? __builtin_amdgcn_exp2f(static_cast<float>(arg)) : 0.0f;
-        const double w = static_cast<double>(w32);
-        const double wy = w * yv;
-        const double wuy = w * uy;
+        const double arg = fma(s0 + s1, kHalfLog2e, fma(kHalfLog2e * vy, vy, kx));
+        const float e = __builtin_amdgcn_exp2f(static_cast<float>(arg));
+        const double w = static_cast<double>(ok ? e : 0.0f);
+        const double yd = static_cast<double>(yv);
+        const double wy = w * yd;
+        const double wvy = w * vy;
         qW += w;
-        qY += wuy;
+        qY += wvy;
         qG += wy;
-        Ayy = fma(wuy, uy, Ayy);
-        gy = fma(wy, uy, gy);
-        Syy = fma(wy, yv, Syy);
+        Ayy = fma(wvy, vy, Ayy);
+        gy = fma(wy, vy, gy);
+        Syy = fma(wy, yd, Syy);
         int qq = 0;
 #pragma unroll
         for (int f = 0; f < F; ++f) {
-          const double wz = w * u[f];
+          const double wz = w * v[f];
           qF[f] += wz;
-          Ayf[f] = fma(wuy, u[f], Ayf[f]);
-          gf[f] = fma(wz, yv, gf[f]);
+          Ayf[f] = fma(wvy, v[f], Ayf[f]);
+          gf[f] = fma(wz, yd, gf[f]);
 #pragma unroll
-          for (int e = f; e < F; ++e) {
-            Aff[qq] = fma(wz, u[e], Aff[qq]);
+          for (int e2 = f; e2 < F; ++e2) {
+            Aff[qq] = fma(wz, v[e2], Aff[qq]);
             ++qq;
           }
         }
+      };
+      float yA, fA[F], yB, fB[F];
+      bool okA = load_row(yA, fA), okB;
+      // two rows per iteration in one basic block (an odd last row is
+      // accumulated with weight 0), so the scheduler can overlap the weight of
+      // one row with the Gram updates of the other
+#pragma unroll 1
+      for (int q = 0; q < nrows; q += 2) {
+        okB = load_row(yB, fB) & (q + 1 < nrows);
+        accumulate(yA, fA, okA);
+        okA = load_row(yA, fA);
+        accumulate(yB, fB, okB);
       }
-      // fold the column pass: every entry with a u_x factor
+      // fold the column pass: every entry with a v_x factor
       SW += qW;
       A0y += qY;
       g0 += qG;
-      A0x = fma(ux, qW, A0x);
-      Axx = fma(ux * ux, qW, Axx);
-      Axy = fma(ux, qY, Axy);
-      gx = fma(ux, qG, gx);
+      A0x = fma(vx, qW, A0x);
+      Axx = fma(vx * vx, qW, Axx);
+      Axy = fma(vx, qY, Axy);
+      gx = fma(vx, qG, gx);
 #pragma unroll
       for (int f = 0; f < F; ++f) {
         A0f[f] += qF[f];
-        Axf[f] = fma(ux, qF[f], Axf[f]);
+        Axf[f] = fma(vx, qF[f], Axf[f]);
       }
     }
 
@@ -263,9 +269,9 @@ regress_kernel(RegressArgs a) {
     M[at(0, 0)] = 1.0;
     M[at(1, 0)] = A0x * iW;
     M[at(2, 0)] = A0y * iW;
-    M[at(1, 1)] = Axx * iW + C.ridge;
+    M[at(1, 1)] = Axx * iW + C.ridge * C.c2[0];
     M[at(2, 1)] = Axy * iW;
-    M[at(2, 2)] = Ayy * iW + C.ridge;
+    M[at(2, 2)] = Ayy * iW + C.ridge * C.c2[1];
     rhs[0] = g0 * iW;
     rhs[1] = gx * iW;
     rhs[2] = gy * iW;
@@ -279,7 +285,7 @@ regress_kernel(RegressArgs a) {
         rhs[3 + f] = gf[f] * iW;
 #pragma unroll
         for (int e = f; e < F; ++e) {
-          M[at(3 + e, 3 + f)] = Aff[q] * iW + (e == f ? C.ridge : 0.0);
+          M[at(3 + e, 3 + f)] = Aff[q] * iW + (e == f ? C.ridge * C.c2[2 + f] : 0.0);
           ++q;
         }
       }
@@ -326,13 +332,13 @@ regress_kernel(RegressArgs a) {
       if (j == 0) {
         a.alpha[idx_out] = static_cast<float>(th[0]);
         if (a.resid) {
-          // at the solution (A + ridge E) theta = rhs, so
-          // R = Syy/W - theta^T rhs - ridge |beta|^2
+          // at the solution (A + Lambda) theta = rhs, so
+          // R = Syy/W - theta^T rhs - theta^T Lambda theta
           double tg = 0.0, bb = 0.0;
 #pragma unroll
           for (int i = 0; i < P; ++i) tg = fma(th[i], rhs[i], tg);
 #pragma unroll
-          for (int i = 1; i < P; ++i) bb = fma(th[i], th[i], bb);
+          for (int i = 1; i < P; ++i) bb = fma(th[i] * C.c2[i - 1], th[i], bb);
           a.resid[idx_out] = static_cast<float>(Syy * iW - tg - C.ridge * bb);
         }
         if (a.kappa) {
@@ -343,7 +349,8 @@ regress_kernel(RegressArgs a) {
       if (a.beta) {
 #pragma unroll
         for (int d = 0; d < D; ++d)
-          if (d % L == j) a.beta[static_cast<int64_t>(d) * a.n_out + idx_out] = static_cast<float>(th[1 + d]);
+          if (d % L == j)
+            a.beta[static_cast<int64_t>(d) * a.n_out + idx_out] = static_cast<float>(th[1 + d] * sf[d]);
       }
     }
     }  // waterfall
@@ -363,6 +370,7 @@ KernelFn pick_lanes(int lanes, bool f16) {
     case 2: return pick_dtype<F, 2>(f16);
     case 4: return pick_dtype<F, 4>(f16);
     case 8: return pick_dtype<F, 8>(f16);
+    case 16: return pick_dtype<F, 16>(f16);
     default: return nullptr;
   }
 }
@@ -387,7 +395,7 @@ KernelFn pick(int F, int lanes, bool f16) {
 
 }  // namespace
 
-int regress_supported_lanes(int F) { return (F >= 1 && F <= ESIM_MAX_F) ? 0x2 | 0x4 | 0x8 : 0; }
+int regress_supported_lanes(int F) { return (F >= 1 && F <= ESIM_MAX_F) ? 0x2 | 0x4 | 0x8 | 0x10 : 0; }
 
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
                           int blocks_per_cu, hipStream_t s) {

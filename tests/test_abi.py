@@ -57,7 +57,7 @@ def test_invalid_arguments_fail_before_any_launch(lib):
     assert lib.esim_events(None, 0, 1, None, None, None, None, None, 0, None, None) == B.E_INVAL
     assert lib.esim_wlr_backward(None, None, 1, None, None, None, None, 0, None) == B.E_INVAL
     assert lib.esim_plan_pixels(None) == -1
-    assert lib.esim_plan_set_schedule(None, 4, 4) == B.E_INVAL
+    assert lib.esim_plan_set_schedule(None, 4, 16, 4) == B.E_INVAL
 
 
 def test_bad_shapes_and_params_are_rejected(lib):
