@@ -89,6 +89,15 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-exhaustive", action="store_true")
     ap.add_argument("--eager", action="store_true", help="time eager launches instead of a graph")
+    ap.add_argument("--save-clip", type=str, default=None,
+                    help="also save the generated clip (E, feat) to this file")
+    ap.add_argument("--load-clip", type=str, default=None,
+                    help="load the clip saved by --save-clip instead of generating it")
+    ap.add_argument("--schedule", type=str, default=None,
+                    help="lanes_dense,lanes_list,blocks_per_cu (skips the autotuner)")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (the "
+                         "known-size reference for HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -115,18 +124,32 @@ def main():
     r, tr, C = cfg["r"], cfg["tr"], cfg["C"]
     T, H, W, F = spec.T, spec.H, spec.W, spec.F
     t0 = time.time()
-    clip = synth.make_clip(spec, device=dev)
-    torch.cuda.synchronize()
-    log(f"generated {W}x{H}x{T} spp={spec.spp} F={F} in {time.time() - t0:.1f}s")
-    E, feat = clip["E"].contiguous(), clip["feat"].contiguous()
+    if args.load_clip:
+        saved = torch.load(args.load_clip, map_location=dev, weights_only=True)
+        E, feat = saved["E"].contiguous(), saved["feat"].contiguous()
+        assert tuple(feat.shape) == (T, F, H, W)
+        log(f"loaded {W}x{H}x{T} clip from {args.load_clip}")
+    else:
+        clip = synth.make_clip(spec, device=dev)
+        torch.cuda.synchronize()
+        log(f"generated {W}x{H}x{T} spp={spec.spp} F={F} in {time.time() - t0:.1f}s")
+        E, feat = clip["E"].contiguous(), clip["feat"].contiguous()
+        if args.save_clip:
+            torch.save({"E": E.cpu(), "feat": feat.cpu()}, args.save_clip)
     y = torch.empty_like(E)
     params = B.Params(r=r, tr=tr, C=C)
     sim = Simulator(y, feat, params)
     pf = T * H * W
     B.log_brightness(E, out=y)
     t0 = time.time()
-    sched = autotune.tune(sim.plan, verbose=False)
-    log(f"autotuned schedule (lanes dense, lanes list, blocks/CU) = {sched} in {time.time() - t0:.1f}s")
+    if args.schedule:
+        sched = tuple(int(v) for v in args.schedule.split(","))
+        sim.plan.set_schedule(*sched)
+        log(f"schedule (lanes dense, lanes list, blocks/CU) = {sched} (given)")
+    else:
+        sched = autotune.tune(sim.plan, verbose=False)
+        log(f"autotuned schedule (lanes dense, lanes list, blocks/CU) = {sched} "
+            f"in {time.time() - t0:.1f}s")
 
     def step(mode):
         B.log_brightness(E, out=y)
@@ -161,12 +184,21 @@ def main():
         ev = sim.events()
         return ms, wall, ev
 
+    if args.copy_probe:
+        a = torch.ones(128 << 20, dtype=torch.float32, device=dev)
+        b = torch.empty_like(a)
+        for _ in range(3):
+            torch.mul(a, 2.0, out=b)
+        torch.cuda.synchronize()
+        del a, b
+        log("copy probe: 3 x (512 MiB read + 512 MiB write)")
+
     ms_thr, wall_thr, ev_thr = timed("thresholded")
-    flagged = sim.flagged.cpu().numpy()[1:]
-    phi = float(flagged.sum()) / ((T - 1) * H * W)
+    # every flagged pixel emits exactly one event, so the flagged fraction is
+    # events / ((T - 1) H W)
+    phi = float(ev_thr["count"]) / ((T - 1) * H * W)
     log(f"thresholded: {ms_thr:.3f} ms/step (wall {wall_thr:.3f}), events {ev_thr['count']}, "
-        f"flagged fraction {phi:.4f} (per-frame min {flagged.min() / (H * W):.4f} "
-        f"max {flagged.max() / (H * W):.4f})")
+        f"flagged fraction {phi:.4f}")
     exh = None
     if not args.no_exhaustive:
         ms_exh, wall_exh, ev_exh = timed("exhaustive")
@@ -175,6 +207,9 @@ def main():
                    events_per_s=ev_exh["count"] / (ms_exh * 1e-3), events=ev_exh["count"])
 
     # ---- roofline of the regression kernel: instrumented eager pass --------
+    # The thresholded path launches the regression kernel twice over: one dense
+    # launch at frame 0 (lanes_dense instance) and one work-list launch per
+    # later frame (lanes_list instance).  The dominant kernel is the list one.
     stream = torch.cuda.current_stream()
     marks = []
     orig = B.regress
@@ -184,7 +219,7 @@ def main():
         s0.record(stream)
         orig(*a, **k)
         s1.record(stream)
-        marks.append((s0, s1))
+        marks.append((a[2] is None, s0, s1))
 
     B.regress = timed_regress
     try:
@@ -193,24 +228,27 @@ def main():
         torch.cuda.synchronize()
     finally:
         B.regress = orig
-    durs = np.array([a.elapsed_time(b) for a, b in marks])     # ms per launch
+    dense_ms = np.array([a.elapsed_time(b) for d, a, b in marks if d])
+    list_ms = np.array([a.elapsed_time(b) for d, a, b in marks if not d])
     ev = sim.events()
-    omega = np.concatenate([
-        omega_sizes(np.arange(H * W) % W, np.arange(H * W) // W, np.zeros(H * W, np.int64),
-                    W, H, T, r, tr),
-        omega_sizes(ev["x"].astype(np.int64), ev["y"].astype(np.int64), ev["t"].astype(np.int64),
-                    W, H, T, r, tr)])
-    flops = regress_flops(omega, F).sum()
-    achieved = flops / (durs.sum() * 1e-3) / 1e12
-    n_launch = len(durs)
+    fl_dense = regress_flops(omega_sizes(np.arange(H * W) % W, np.arange(H * W) // W,
+                                         np.zeros(H * W, np.int64), W, H, T, r, tr), F).sum()
+    fl_list = regress_flops(omega_sizes(ev["x"].astype(np.int64), ev["y"].astype(np.int64),
+                                        ev["t"].astype(np.int64), W, H, T, r, tr), F).sum()
+    achieved = fl_list / (list_ms.sum() * 1e-3) / 1e12
     traffic = traffic_from_profile(None)
+    ld, ll, bpc = sched
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": PEAK_ALU_TFLOPS,
             "unit": "TFLOP/s", "frac": round(achieved / PEAK_ALU_TFLOPS, 4),
-            "traffic": traffic, "kernel": "regress_kernel<F=7,L=4,f32>",
-            "launches": n_launch, "avg_launch_ms": round(float(durs.mean()), 4),
-            "flop_per_launch": float(flops / n_launch),
-            "regress_share_of_step": round(float(durs.sum()) / ms_thr, 3)}
-    log(f"regress: {n_launch} launches, {durs.sum():.3f} ms total, {achieved:.2f} TFLOP/s")
+            "traffic": traffic, "kernel": f"regress_kernel<F={F},L={ll},f32> (work-list launches)",
+            "launches": int(list_ms.size), "avg_launch_ms": round(float(list_ms.mean()), 4),
+            "flop_per_launch": float(fl_list / list_ms.size),
+            "regress_share_of_step": round(float(list_ms.sum() + dense_ms.sum()) / ms_thr, 3),
+            "dense_frame0": {"kernel": f"regress_kernel<F={F},L={ld},f32>",
+                             "ms": round(float(dense_ms.sum()), 4),
+                             "tflops": round(fl_dense / (dense_ms.sum() * 1e-3) / 1e12, 3)}}
+    log(f"regress list launches: {list_ms.size}, avg {list_ms.mean():.4f} ms, {achieved:.2f} TFLOP/s; "
+        f"dense frame 0: {dense_ms.sum():.3f} ms")
 
     # ---- dense (exhaustive) regression roofline, same method ---------------
     if exh is not None:
@@ -221,7 +259,7 @@ def main():
             torch.cuda.synchronize()
         finally:
             B.regress = orig
-        d2 = np.array([a.elapsed_time(b) for a, b in marks])
+        d2 = np.array([a.elapsed_time(b) for _, a, b in marks])
         tt = np.repeat(np.arange(T, dtype=np.int64), H * W)
         om = omega_sizes(np.tile(np.arange(H * W) % W, T), np.tile(np.arange(H * W) // W, T), tt,
                          W, H, T, r, tr)

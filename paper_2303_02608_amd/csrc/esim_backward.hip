@@ -1,6 +1,312 @@
-// placeholder: adjoint kernels
-#include "esim_internal.h"
+// Adjoint of the regression estimate alpha (Sec. 2.1, eqs. 4-5 differentiated).
+//
+// With A the W-normalised Gram plus ridge Lambda (in bandwidth-scaled units),
+// theta = A^{-1} g, v = A^{-1} e_0, s_i = v^T z_i and r_i = y_i - z_i^T theta:
+//     d alpha / d y_i = (w_i / W) s_i
+//     d alpha / d w_i = (s_i r_i - v^T Lambda theta) / W
+//     d w_i / d b_j   = w_i u_ij^2 / (h^2 b_j^3) = w_i v_ij^2 / b_j
+// (alpha does not depend on the scaling of the regressors, so the scaled system
+// gives the same derivatives).
+//
+// Kernels, all deterministic (no atomics on values):
+//   fill_map / map_items  a dense (frame, pixel) -> item index map
+//   adjoint_kernel        per item: recompute the window, Gram, Cholesky,
+//                         theta and v (the window is not stored by the forward
+//                         pass); a second window pass writes each sample's
+//                         contribution g_alpha (w_i / W) s_i to the item's slot
+//                         and sums the bandwidth gradient over the item's lanes
+//   gather_kernel         per input (frame, pixel): sums, in a fixed order, the
+//                         contributions of every item whose window holds it
+//   reduce_gb_*           fixed-order two-level sum of the per-item b gradients
+#include "esim_wlr.h"
+
 namespace esim {
-size_t backward_scratch_bytes(const ClipDev& hc, int64_t n) { (void)hc; return static_cast<size_t>(n) * 8; }
-hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) { (void)a; (void)s; return hipErrorNotSupported; }
+namespace {
+
+constexpr int kAdjLanes = 4;
+constexpr int kRedBlocks = 256;
+
+struct BwdDev {
+  int32_t* item_map;   // [T*HW]
+  float* contrib;      // [n][S]
+  double* gbpart;      // [n][D]
+  double* gbblk;       // [kRedBlocks][D]
+  int64_t S;           // window slots per item: (2r+1)^2 (2tr+1)
+  int64_t n;
+};
+
+__global__ void __launch_bounds__(256) fill_map_kernel(int32_t* m, int64_t n) {
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) m[i] = -1;
 }
+
+__device__ __forceinline__ bool item_ok(const ClipDev& C, int64_t it, const float* g_alpha, int64_t i,
+                                        int64_t& pix, int& t) {
+  if (it < 0 || item_clip(it) != 0) return false;
+  pix = item_pixel(it);
+  t = item_frame(it);
+  return pix < C.HW && t >= 0 && t < C.T && g_alpha[i] != 0.0f;
+}
+
+__global__ void __launch_bounds__(256)
+map_items_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ items, int64_t n,
+                 const float* __restrict__ g_alpha, int32_t* item_map) {
+  const ClipDev& C = clips[0];
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    int64_t pix;
+    int t;
+    if (item_ok(C, items[i], g_alpha, i, pix, t)) item_map[static_cast<int64_t>(t) * C.HW + pix] = static_cast<int32_t>(i);
+  }
+}
+
+template <int F, int L, bool F16>
+__global__ void __launch_bounds__(256)
+adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ items,
+               const float* __restrict__ g_alpha, BwdDev bd) {
+  constexpr int D = F + 2;
+  constexpr int P = F + 3;
+  constexpr int G = kWave / L;
+  const ClipDev& C = clips[0];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = lane / L;
+  const int j = lane % L;
+  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
+  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) / kWave;
+  const int64_t ngroups = (bd.n + G - 1) / G;
+  const int r = C.r, tr = C.tr;
+  const int span = 2 * r + 1;
+  for (int64_t g = wave; g < ngroups; g += nwaves) {
+    const int64_t i = g * G + slot;
+    int64_t pix = 0;
+    int t = 0;
+    const bool active = i < bd.n && item_ok(C, items[i], g_alpha, i, pix, t);
+    if (__ballot(active) == 0) {
+      if (i < bd.n && j == 0)
+        for (int d = 0; d < D; ++d) bd.gbpart[i * D + d] = 0.0;
+      continue;
+    }
+    ItemGeom<F, F16> geo;
+    make_geom(geo, C, active ? pix : 0, active ? t : 0, 0, C.T, active);
+
+    Gram<F> gm;
+    gm.zero();
+    window_loop<F, L, F16>(
+        geo, j, [&](double) { gm.pass_begin(); },
+        [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+          gm.add(w, yd, v, vy);
+        },
+        [&](double vx) { gm.pass_end(vx); });
+    gm.template lane_sum<L>();
+    double M[P * (P + 1) / 2], rhs[P], th[P], dmin, dmax;
+    const double iW = gram_solve<F>(gm, C, M, rhs, th, dmin, dmax);
+    double e0[P], vv[P];
+#pragma unroll
+    for (int k = 0; k < P; ++k) e0[k] = k == 0 ? 1.0 : 0.0;
+    chol_solve<P>(M, e0, vv);
+    double vLt = 0.0;      // v^T Lambda theta (Lambda = scaled ridge on the beta block)
+#pragma unroll
+    for (int k = 1; k < P; ++k) vLt = fma(vv[k] * (C.ridge * C.c2[k - 1]), th[k], vLt);
+    const double ga = active ? static_cast<double>(g_alpha[i]) : 0.0;
+    float* ci = bd.contrib + (active ? i : 0) * bd.S;
+
+    double gb[D];
+#pragma unroll
+    for (int d = 0; d < D; ++d) gb[d] = 0.0;
+    double cur_vx = 0.0;
+    window_loop<F, L, F16>(
+        geo, j, [&](double vx) { cur_vx = vx; },
+        [&](double w, double yd, const double (&v)[F], double vy, int dx, int dt, int dy, bool ok) {
+          double s = fma(vv[1], cur_vx, fma(vv[2], vy, vv[0]));
+          double pred = fma(th[1], cur_vx, fma(th[2], vy, th[0]));
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            s = fma(vv[3 + f], v[f], s);
+            pred = fma(th[3 + f], v[f], pred);
+          }
+          const double res = yd - pred;
+          // only in-image samples have a slot the gather reads; the padding
+          // row of an odd row count lies past the window and is skipped
+          if (ok) ci[((dt + tr) * span + (dy + r)) * span + (dx + r)] = static_cast<float>(ga * w * iW * s);
+          const double k = ga * (s * res - vLt) * iW * w;
+          gb[0] = fma(k, cur_vx * cur_vx, gb[0]);
+          gb[1] = fma(k, vy * vy, gb[1]);
+#pragma unroll
+          for (int f = 0; f < F; ++f) gb[2 + f] = fma(k, v[f] * v[f], gb[2 + f]);
+        },
+        [&](double) {});
+#pragma unroll
+    for (int d = 0; d < D; ++d) gb[d] = group_sum<L>(gb[d]);
+    if (i < bd.n && j == 0) {
+#pragma unroll
+      for (int d = 0; d < D; ++d)
+        bd.gbpart[i * D + d] = active ? gb[d] * C.sf[d] * C.h : 0.0;   // / b_d = * sf_d * h
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256)
+gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ g_y) {
+  const ClipDev& C = clips[0];
+  const int r = C.r, tr = C.tr, W = C.W, H = C.H, T = C.T;
+  const int span = 2 * r + 1;
+  const int64_t N = static_cast<int64_t>(T) * C.HW;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; q < N; q += stride) {
+    const int tq = static_cast<int>(q / C.HW);
+    const int64_t p = q - static_cast<int64_t>(tq) * C.HW;
+    const int yq = static_cast<int>(p / W), xq = static_cast<int>(p - static_cast<int64_t>(yq) * W);
+    double acc = 0.0;
+    const int t0 = max(0, tq - tr), t1 = min(T - 1, tq + tr);
+    const int y0 = max(0, yq - r), y1 = min(H - 1, yq + r);
+    const int x0 = max(0, xq - r), x1 = min(W - 1, xq + r);
+    for (int tc = t0; tc <= t1; ++tc)
+      for (int yc = y0; yc <= y1; ++yc) {
+        const int32_t* row = bd.item_map + static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W;
+        const int base = ((tq - tc + tr) * span + (yq - yc + r)) * span + xq + r;
+        for (int xc = x0; xc <= x1; ++xc) {
+          const int32_t it = row[xc];
+          if (it >= 0) acc += static_cast<double>(bd.contrib[static_cast<int64_t>(it) * bd.S + (base - xc)]);
+        }
+      }
+    if (acc != 0.0) g_y[q] += static_cast<float>(acc);
+  }
+}
+
+template <int D>
+__global__ void __launch_bounds__(256) reduce_gb_blocks(BwdDev bd) {
+  __shared__ double sh[256][D];
+  double acc[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) acc[d] = 0.0;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < bd.n;
+       i += static_cast<int64_t>(gridDim.x) * 256)
+#pragma unroll
+    for (int d = 0; d < D; ++d) acc[d] += bd.gbpart[i * D + d];
+#pragma unroll
+  for (int d = 0; d < D; ++d) sh[threadIdx.x][d] = acc[d];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (static_cast<int>(threadIdx.x) < o)
+#pragma unroll
+      for (int d = 0; d < D; ++d) sh[threadIdx.x][d] += sh[threadIdx.x + o][d];
+    __syncthreads();
+  }
+  if (threadIdx.x < D) bd.gbblk[blockIdx.x * D + threadIdx.x] = sh[0][threadIdx.x];
+}
+
+__global__ void reduce_gb_final(BwdDev bd, int nblk, int D, double* g_b) {
+  const int d = threadIdx.x;
+  if (d >= D) return;
+  double s = 0.0;
+  for (int b = 0; b < nblk; ++b) s += bd.gbblk[b * D + d];
+  g_b[d] += s;
+}
+
+using AdjFn = void (*)(const ClipDev*, const int64_t*, const float*, BwdDev);
+
+template <int F>
+AdjFn pick_adj(bool f16) {
+  return f16 ? adjoint_kernel<F, kAdjLanes, true> : adjoint_kernel<F, kAdjLanes, false>;
+}
+
+AdjFn pick(int F, bool f16) {
+  switch (F) {
+    case 1: return pick_adj<1>(f16);
+    case 2: return pick_adj<2>(f16);
+    case 3: return pick_adj<3>(f16);
+    case 4: return pick_adj<4>(f16);
+    case 5: return pick_adj<5>(f16);
+    case 6: return pick_adj<6>(f16);
+    case 7: return pick_adj<7>(f16);
+    case 8: return pick_adj<8>(f16);
+    case 9: return pick_adj<9>(f16);
+    case 10: return pick_adj<10>(f16);
+    case 11: return pick_adj<11>(f16);
+    case 12: return pick_adj<12>(f16);
+    default: return nullptr;
+  }
+}
+
+using RedFn = void (*)(BwdDev);
+template <int D>
+RedFn red() { return reduce_gb_blocks<D>; }
+RedFn pick_red(int D) {
+  switch (D) {
+    case 3: return red<3>();
+    case 4: return red<4>();
+    case 5: return red<5>();
+    case 6: return red<6>();
+    case 7: return red<7>();
+    case 8: return red<8>();
+    case 9: return red<9>();
+    case 10: return red<10>();
+    case 11: return red<11>();
+    case 12: return red<12>();
+    case 13: return red<13>();
+    case 14: return red<14>();
+    default: return nullptr;
+  }
+}
+
+size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
+
+struct Layout {
+  size_t map, contrib, gbpart, gbblk, total;
+  int64_t S;
+};
+
+Layout layout(const ClipDev& hc, int64_t n) {
+  Layout l{};
+  const int D = hc.F + 2;
+  l.S = static_cast<int64_t>(2 * hc.r + 1) * (2 * hc.r + 1) * (2 * hc.tr + 1);
+  size_t off = 0;
+  l.map = off;
+  off = align256(off + sizeof(int32_t) * static_cast<size_t>(hc.T) * hc.HW);
+  l.contrib = off;
+  off = align256(off + sizeof(float) * static_cast<size_t>(n) * l.S);
+  l.gbpart = off;
+  off = align256(off + sizeof(double) * static_cast<size_t>(n) * D);
+  l.gbblk = off;
+  off = align256(off + sizeof(double) * kRedBlocks * D);
+  l.total = off;
+  return l;
+}
+
+unsigned grid_for(int64_t n, int64_t cap) {
+  int64_t b = (n + 255) / 256;
+  if (b > cap) b = cap;
+  if (b < 1) b = 1;
+  return static_cast<unsigned>(b);
+}
+
+}  // namespace
+
+size_t backward_scratch_bytes(const ClipDev& hc, int64_t n) { return layout(hc, n).total; }
+
+hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
+  const ClipDev& hc = *a.host_clip;
+  const int F = hc.F, D = F + 2;
+  AdjFn adj = pick(F, hc.feat_f16 != 0);
+  RedFn rb = pick_red(D);
+  if (!adj || !rb) return hipErrorInvalidValue;
+  const Layout l = layout(hc, a.n);
+  char* m = static_cast<char*>(a.scratch);
+  BwdDev bd{reinterpret_cast<int32_t*>(m + l.map), reinterpret_cast<float*>(m + l.contrib),
+            reinterpret_cast<double*>(m + l.gbpart), reinterpret_cast<double*>(m + l.gbblk), l.S, a.n};
+  const int64_t map_n = static_cast<int64_t>(hc.T) * hc.HW;
+  hipLaunchKernelGGL(fill_map_kernel, dim3(grid_for(map_n, 4096)), dim3(256), 0, s, bd.item_map, map_n);
+  hipLaunchKernelGGL(map_items_kernel, dim3(grid_for(a.n, 4096)), dim3(256), 0, s, a.clip, a.items, a.n,
+                     a.g_alpha, bd.item_map);
+  const int G = kWave / kAdjLanes;
+  int64_t blocks = ((a.n + G - 1) / G + kWavesPerBlock - 1) / kWavesPerBlock;
+  if (blocks > 1024) blocks = 1024;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a.clip, a.items, a.g_alpha, bd);
+  hipLaunchKernelGGL(gather_kernel, dim3(grid_for(map_n, 8192)), dim3(256), 0, s, a.clip, bd, a.g_y);
+  hipLaunchKernelGGL(rb, dim3(kRedBlocks), dim3(256), 0, s, bd);
+  hipLaunchKernelGGL(reduce_gb_final, dim3(1), dim3(64), 0, s, bd, kRedBlocks, D, a.g_b);
+  return hipGetLastError();
+}
+
+}  // namespace esim

@@ -15,7 +15,8 @@
 //                      lane; writes the work list (threshold) or the events.
 //   list_events_kernel events of the work-list items and the state update
 //                      (Sec. 2.2: the model at the last event is kept until the
-//                      pixel's next event).
+//                      pixel's next event); its last block advances the
+//                      event count.
 //   init_kernel        state <- the models of frame t (no events).
 #include "esim_internal.h"
 #include "esim_compact.h"
@@ -202,6 +203,12 @@ scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, W
   }
 }
 
+__device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, int t,
+                                 const int64_t* __restrict__ worklist, int64_t n, int64_t base,
+                                 int64_t stride, const float* __restrict__ dl,
+                                 const float* __restrict__ alpha, const float* __restrict__ beta,
+                                 int64_t n_out, const Workspace& ws, const EventsDev& ev);
+
 __global__ void __launch_bounds__(256)
 list_events_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const int64_t* __restrict__ worklist,
                    const int32_t* __restrict__ count, const float* __restrict__ dl,
@@ -212,6 +219,29 @@ list_events_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const i
                         min(static_cast<int64_t>(count[0]), min(max_items, n_out)));
   const int64_t base = *ev.count;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  list_events_body(clips, nclips, t, worklist, n, base, stride, dl, alpha, beta, n_out, ws, ev);
+  // The last block to finish advances the event count; every block has read
+  // the count above before taking its ticket, so no block sees the new value.
+  __shared__ bool last;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();
+    const unsigned int done = atomicAdd(reinterpret_cast<unsigned int*>(ws.misc + 1), 1u);
+    last = done == gridDim.x - 1;
+  }
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    *ev.count = base + count[1];
+    ws.misc[1] = 0;   // re-arm the ticket for the next launch
+    __threadfence();
+  }
+}
+
+__device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, int t,
+                                 const int64_t* __restrict__ worklist, int64_t n, int64_t base,
+                                 int64_t stride, const float* __restrict__ dl,
+                                 const float* __restrict__ alpha, const float* __restrict__ beta,
+                                 int64_t n_out, const Workspace& ws, const EventsDev& ev) {
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
     const int64_t it = worklist[i];
     if (it < 0) continue;
@@ -237,8 +267,6 @@ list_events_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const i
     C.st_tref[p] = t;
   }
 }
-
-__global__ void advance_kernel(int64_t* ev_count, const int32_t* count) { *ev_count += count[1]; }
 
 __global__ void __launch_bounds__(kBlock)
 init_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const float* __restrict__ alpha,
@@ -291,11 +319,10 @@ hipError_t launch_list_events(const ClipDev* clips, int nclips, int t, const int
                               const float* alpha, const float* beta, int64_t n_out,
                               const Workspace& ws, const EventsDev& ev, hipStream_t s) {
   int64_t blocks = (max_items + 255) / 256;
-  if (blocks > 4096) blocks = 4096;
+  if (blocks > 512) blocks = 512;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(list_events_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, clips,
                      nclips, t, worklist, count, dl, alpha, beta, n_out, max_items, ws, ev);
-  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(1), 0, s, ev.count, count);
   return hipGetLastError();
 }
 

@@ -43,7 +43,7 @@ struct Workspace {
   uint64_t* pol;           // [nblk][kWavesPerBlock] positive-polarity ballots
   int64_t* seg_start;      // [nclips] first work-list entry of each clip
   int64_t* seg_prefix;     // [nclips] flagged pixels of the clips before
-  int64_t* misc;           // [4] ev_base of the last list-event call, ...
+  int64_t* misc;           // [4] [0] event base of the last scan, [1] block ticket
 };
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {

@@ -40,12 +40,13 @@ class Simulator:
         if capacity is None:
             capacity = min(T * self.HW, 1 << 26)
         self.ev = B.Events(capacity, dev)
+        # per-frame flagged counts (only recorded when asked: it adds a copy per frame)
         self.flagged = torch.zeros(T, dtype=torch.int32, device=dev)
         self.graph = None
         self.graph_mode = None
 
     # -- one conversion, enqueued on the current stream --------------------
-    def enqueue(self, mode: str = "thresholded", record_flags: bool = True):
+    def enqueue(self, mode: str = "thresholded", record_flags: bool = False):
         if mode not in MODES:
             raise ValueError(mode)
         p, n = self.plan, self.HW

@@ -60,9 +60,10 @@ def test_thresholded_flags_fraction_and_order(small_clip):
     say("flag fraction")
     y, fd = to_dev(E, feat)
     sim = Simulator(y, fd, p)
-    sim.enqueue("thresholded")
+    sim.enqueue("thresholded", record_flags=True)
     torch.cuda.synchronize()
     fl = sim.flagged.cpu().numpy()[1:]
+    assert fl.sum() == sim.events()["count"]
     frac = fl.sum() / ((sim.T - 1) * sim.HW)
     assert 0.01 < frac < 0.5
     orc = _oracle_run(E, feat, p, "thresholded")
