@@ -65,8 +65,11 @@ typedef enum {
 /* Gram precision of the regression */
 typedef enum {
   ESIM_GRAM_F64 = 0,      /* FP32 weights, FP64 Gram and FP64 Cholesky (default) */
-  ESIM_GRAM_F32C = 1      /* FP32 Gram with compensated sums, FP32 Cholesky,
-                             FP64 re-solve when kappa-hat > kappa_fp64          */
+  ESIM_GRAM_F32C = 1      /* FP32 regressors and weights, FP32 Gram with
+                             block-compensated (Neumaier) sums, FP32 Cholesky,
+                             FP64 re-solve of the compensated Gram when the
+                             Hager condition estimate exceeds kappa_fp64.
+                             Compiled for F in {7, 10}, lanes 4 and 16.        */
 } esim_precision;
 
 /* One clip.  y = log brightness [T][H][W] (see esim_log_brightness); feat =
@@ -179,11 +182,14 @@ int esim_wlr_threshold(esim_plan plan, int32_t t, float* dl, int64_t* worklist,
  *   beta[d * n_out + i] (nullable) = gradient over the D = F + 2 features,
  *                       coordinates first,
  *   resid[i] (nullable) = R of eq. (4) at the minimiser,
- *   kappa[i] (nullable) = kappa-hat: (max L_jj / min L_jj)^2 of the Cholesky
- *                       factor of the W-normalised Gram in bandwidth-scaled
- *                       regressors u_j / (h b_j), a lower bound of that
- *                       system's 2-norm condition number (the unscaled system
- *                       when all bandwidths are 1).
+ *   kappa[i] (nullable) = kappa-hat: ||A||_1 times Hager's estimate of
+ *                       ||A^{-1}||_1 on the Cholesky factor, A the W-normalised
+ *                       Gram plus ridge in bandwidth-scaled regressors
+ *                       u_j / (h b_j) (the unscaled system when all bandwidths
+ *                       are 1); a lower bound of the 1-norm condition number.
+ *                       With ESIM_GRAM_F32C it is the FP32 estimate that
+ *                       decides the FP64 re-solve (re-solved iff it exceeds
+ *                       kappa_fp64 or is not finite).
  * Errors: E_INVAL (null outputs, n_out too small for dense mode),
  * E_UNSUPPORTED (t < 0 with a clip of 4 GiB or more of features). */
 int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const int32_t* count,

@@ -84,7 +84,10 @@ def tune(plan: B.Plan, frames: int = 12, lanes_dense: Iterable[int] = (2, 4, 8),
     for ld, ll, bpc in itertools.product(lanes_dense, lanes_list, blocks_per_cu):
         if ld != 4 and ll != 16:
             continue          # lanes_dense is tuned along one line only
-        plan.set_schedule(ld, ll, bpc)
+        try:
+            plan.set_schedule(ld, ll, bpc)
+        except B.EsimError:
+            continue          # no kernel instance for this combination
         _time_prefix(plan, frames, bufs)            # warm-up
         d = l = float("inf")
         for _ in range(reps):
@@ -100,6 +103,8 @@ def tune(plan: B.Plan, frames: int = 12, lanes_dense: Iterable[int] = (2, 4, 8),
     nlist = max(1, (frames - 1) - (frames - 1) // 2)
     best = None
     for bpc in blocks_per_cu:
+        if not any(b_ == bpc for (_, b_) in best_dense):
+            continue
         dl_ = min((v, L) for (L, b_), v in best_dense.items() if b_ == bpc)
         ll_ = min((v, L) for (L, b_), v in best_list.items() if b_ == bpc)
         total = dl_[0] + ll_[0] / nlist * (T - 1)

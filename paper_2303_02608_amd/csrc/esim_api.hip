@@ -69,7 +69,8 @@ const char* esim_status_string(int s) {
 const char* esim_last_error(void) { return g_last_error.c_str(); }
 
 const char* esim_build_info(void) {
-  return "libesim gfx950; regress: F=1..12 x lanes{2,4,8,16} x {f32,f16} features, FP64 Gram";
+  return "libesim gfx950; regress: F=1..12 x lanes{2,4,8,16} x {f32,f16} features, FP64 Gram; "
+         "compensated FP32 Gram for F in {7,10} x lanes {4,16}";
 }
 
 int esim_plan_create(const esim_clip* clips, const esim_params* params, const esim_state* states,
@@ -118,6 +119,10 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       if (p.precision != ESIM_GRAM_F64 && p.precision != ESIM_GRAM_F32C) {
         delete pl;
         return fail(ESIM_E_INVAL, "bad precision");
+      }
+      if (c > 0 && p.precision != params[0].precision) {
+        delete pl;
+        return fail(ESIM_E_UNSUPPORTED, "all clips of a plan share the precision");
       }
       for (int d = 0; d < k.F + 2; ++d)
         if (!(p.b[d] > 0) || std::isinf(p.b[d])) {
@@ -282,6 +287,8 @@ int esim_wlr_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int
     if (t < 0 && pl->max_feat_bytes >= (1ull << 32))
       return fail(ESIM_E_UNSUPPORTED, "per-item frames need feature arrays below 4 GiB");
     const int L = worklist ? pl->lanes_list : pl->lanes_dense;
+    if (!esim::regress_supports(pl->F, L, pl->host[0].precision))
+      return fail(ESIM_E_UNSUPPORTED, "no kernel instance for this F, lane count and precision");
     esim::RegressArgs a{};
     a.clips = pl->dev;
     a.nclips = pl->nclips;
@@ -375,9 +382,9 @@ int esim_wlr_backward(esim_plan pl, const int64_t* items, int64_t n, const float
 int esim_plan_set_schedule(esim_plan pl, int32_t lanes_dense, int32_t lanes_list,
                            int32_t blocks_per_cu) {
   if (!pl) return fail(ESIM_E_INVAL, "null plan");
-  const int sup = esim::regress_supported_lanes(pl->F);
   for (int L : {lanes_dense, lanes_list})
-    if (L < 1 || (L & (L - 1)) || !(sup & L)) return fail(ESIM_E_UNSUPPORTED, "lanes per item not compiled");
+    if (L < 1 || (L & (L - 1)) || !esim::regress_supports(pl->F, L, pl->host[0].precision))
+      return fail(ESIM_E_UNSUPPORTED, "lanes per item not compiled for this F and precision");
   if (blocks_per_cu < 1 || blocks_per_cu > 64) return fail(ESIM_E_INVAL, "blocks_per_cu outside 1..64");
   pl->lanes_dense = lanes_dense;
   pl->lanes_list = lanes_list;

@@ -86,24 +86,24 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
         for (int d = 0; d < D; ++d) bd.gbpart[i * D + d] = 0.0;
       continue;
     }
-    ItemGeom<F, F16> geo;
+    ItemGeom<F, F16, double> geo;
     make_geom(geo, C, active ? pix : 0, active ? t : 0, 0, C.T, active);
 
-    Gram<F> gm;
+    Gram<F, double> gm;
     gm.zero();
-    window_loop<F, L, F16>(
+    window_loop<F, L, F16, double>(
         geo, j, [&](double) { gm.pass_begin(); },
         [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
           gm.add(w, yd, v, vy);
         },
         [&](double vx) { gm.pass_end(vx); });
     gm.template lane_sum<L>();
-    double M[P * (P + 1) / 2], rhs[P], th[P], dmin, dmax;
-    const double iW = gram_solve<F>(gm, C, M, rhs, th, dmin, dmax);
+    double M[P * (P + 1) / 2], rhs[P], th[P], anorm;
+    const double iW = gram_solve<F, double>(gm, C, M, rhs, th, anorm);
     double e0[P], vv[P];
 #pragma unroll
     for (int k = 0; k < P; ++k) e0[k] = k == 0 ? 1.0 : 0.0;
-    chol_solve<P>(M, e0, vv);
+    chol_solve<P, double>(M, e0, vv);
     double vLt = 0.0;      // v^T Lambda theta (Lambda = scaled ridge on the beta block)
 #pragma unroll
     for (int k = 1; k < P; ++k) vLt = fma(vv[k] * (C.ridge * C.c2[k - 1]), th[k], vLt);
@@ -114,7 +114,7 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
 #pragma unroll
     for (int d = 0; d < D; ++d) gb[d] = 0.0;
     double cur_vx = 0.0;
-    window_loop<F, L, F16>(
+    window_loop<F, L, F16, double>(
         geo, j, [&](double vx) { cur_vx = vx; },
         [&](double w, double yd, const double (&v)[F], double vy, int dx, int dt, int dy, bool ok) {
           double s = fma(vv[1], cur_vx, fma(vv[2], vy, vv[0]));

@@ -139,6 +139,7 @@ struct RegressArgs {
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
                           int blocks_per_cu, hipStream_t s);
 int regress_supported_lanes(int F);
+bool regress_supports(int F, int lanes, int precision);
 
 struct BackwardArgs {
   const ClipDev* clip;      // single clip (device)

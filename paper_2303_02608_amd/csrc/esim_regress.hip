@@ -23,18 +23,26 @@
 //
 // After the window loop the L lane partials are summed with DPP, every lane of
 // the item factors the (F+3)x(F+3) system redundantly (registers only) and the
-// lanes share the output writes.
+// lanes share the output writes.  The optional condition output is Hager's
+// 1-norm estimate on the factor.
+#include <type_traits>
+
 #include "esim_wlr.h"
 
 namespace esim {
 namespace {
 
-template <int F, int L, bool F16>
+// C32 selects the reduced-precision variant: FP32 regressors and weights,
+// FP32 Gram with block-compensated sums (GramC), FP32 Cholesky, and an FP64
+// re-solve of the same compensated Gram for items whose Hager condition
+// estimate exceeds kappa_fp64.
+template <int F, int L, bool F16, bool C32>
 __global__ void __launch_bounds__(256)
 regress_kernel(RegressArgs a) {
   constexpr int D = F + 2;
   constexpr int P = F + 3;
   constexpr int G = kWave / L;
+  using Real = typename std::conditional<C32, float, double>::type;
 
   const int lane = threadIdx.x & (kWave - 1);
   const int slot = lane / L;
@@ -92,21 +100,62 @@ regress_kernel(RegressArgs a) {
       const int f0 = a.t >= 0 ? max(0, a.t - C.tr) : 0;
       const int f1 = a.t >= 0 ? min(C.T, a.t + C.tr + 1) : C.T;
       // inactive lanes read a valid centre pixel of the resource window
-      ItemGeom<F, F16> geo;
+      ItemGeom<F, F16, Real> geo;
       make_geom(geo, C, active ? my_pix : 0, active ? my_t : (a.t >= 0 ? a.t : 0), f0, f1, active);
 
-      Gram<F> gm;
-      gm.zero();
-      window_loop<F, L, F16>(
-          geo, j, [&](double) { gm.pass_begin(); },
-          [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-            gm.add(w, yd, v, vy);
-          },
-          [&](double vx) { gm.pass_end(vx); });
-      gm.template lane_sum<L>();
-
-      double M[P * (P + 1) / 2], rhs[P], th[P], dmin, dmax;
-      const double iW = gram_solve<F>(gm, C, M, rhs, th, dmin, dmax);
+      double th[P], rhs[P], Syy, iW, kap = 0.0;
+      if constexpr (!C32) {
+        Gram<F, double> gm;
+        gm.zero();
+        window_loop<F, L, F16, double>(
+            geo, j, [&](double) { gm.pass_begin(); },
+            [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+              gm.add(w, yd, v, vy);
+            },
+            [&](double vx) { gm.pass_end(vx); });
+        gm.template lane_sum<L>();
+        double M[P * (P + 1) / 2], anorm;
+        iW = gram_solve<F, double>(gm, C, M, rhs, th, anorm);
+        Syy = gm.Syy;
+        if (a.kappa) kap = anorm * hager_inv_norm1<P, double>(M);
+      } else {
+        GramC<F> gc;
+        gc.zero();
+        window_loop<F, L, F16, float>(
+            geo, j, [&](float) { gc.pass_begin(); },
+            [&](float w, float yd, const float (&v)[F], float vy, int, int, int, bool) {
+              gc.add(w, yd, v, vy);
+            },
+            [&](float vx) { gc.pass_end(vx); });
+        gc.template lane_sum<L>();
+        Gram<F, float> g32;
+        gc.values(g32);
+        float M32[P * (P + 1) / 2], r32[P], t32[P], an32;
+        iW = gram_solve<F, float>(g32, C, M32, r32, t32, an32);
+        kap = static_cast<double>(an32) * static_cast<double>(hager_inv_norm1<P, float>(M32));
+        const bool fallback = !(kap <= C.kappa_fp64);
+        Syy = g32.Syy;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          th[i] = t32[i];
+          rhs[i] = r32[i];
+        }
+        if (__ballot(fallback && active) != 0) {
+          Gram<F, double> g64;
+          gc.values(g64);
+          double M[P * (P + 1) / 2], r64[P], t64[P], an64;
+          const double iW64 = gram_solve<F, double>(g64, C, M, r64, t64, an64);
+          if (fallback) {
+            iW = iW64;
+            Syy = g64.Syy;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+              th[i] = t64[i];
+              rhs[i] = r64[i];
+            }
+          }
+        }
+      }
 
       // ---- outputs (the lanes of an item share the writes)
       if (active) {
@@ -120,18 +169,15 @@ regress_kernel(RegressArgs a) {
             for (int i = 0; i < P; ++i) tg = fma(th[i], rhs[i], tg);
 #pragma unroll
             for (int i = 1; i < P; ++i) bb = fma(th[i] * C.c2[i - 1], th[i], bb);
-            a.resid[idx_out] = static_cast<float>(gm.Syy * iW - tg - C.ridge * bb);
+            a.resid[idx_out] = static_cast<float>(Syy * iW - tg - C.ridge * bb);
           }
-          if (a.kappa) {
-            const double q = dmax / dmin;
-            a.kappa[idx_out] = static_cast<float>(q * q);
-          }
+          if (a.kappa) a.kappa[idx_out] = static_cast<float>(kap);
         }
         if (a.beta) {
 #pragma unroll
           for (int d = 0; d < D; ++d)
             if (d % L == j)
-              a.beta[static_cast<int64_t>(d) * a.n_out + idx_out] = static_cast<float>(th[1 + d] * geo.sf[d]);
+              a.beta[static_cast<int64_t>(d) * a.n_out + idx_out] = static_cast<float>(th[1 + d] * C.sf[d]);
         }
       }
     }  // waterfall
@@ -142,7 +188,17 @@ using KernelFn = void (*)(RegressArgs);
 
 template <int F, int L>
 KernelFn pick_dtype(bool f16) {
-  return f16 ? regress_kernel<F, L, true> : regress_kernel<F, L, false>;
+  return f16 ? regress_kernel<F, L, true, false> : regress_kernel<F, L, false, false>;
+}
+
+// The compensated-FP32 variant is compiled for the feature counts of the
+// workloads (7 and 10) and for the default lane counts.
+KernelFn pick_c32(int F, int lanes, bool f16) {
+  if (F == 7 && lanes == 4) return f16 ? regress_kernel<7, 4, true, true> : regress_kernel<7, 4, false, true>;
+  if (F == 7 && lanes == 16) return f16 ? regress_kernel<7, 16, true, true> : regress_kernel<7, 16, false, true>;
+  if (F == 10 && lanes == 4) return f16 ? regress_kernel<10, 4, true, true> : regress_kernel<10, 4, false, true>;
+  if (F == 10 && lanes == 16) return f16 ? regress_kernel<10, 16, true, true> : regress_kernel<10, 16, false, true>;
+  return nullptr;
 }
 
 template <int F>
@@ -178,10 +234,14 @@ KernelFn pick(int F, int lanes, bool f16) {
 
 int regress_supported_lanes(int F) { return (F >= 1 && F <= ESIM_MAX_F) ? 0x2 | 0x4 | 0x8 | 0x10 : 0; }
 
+bool regress_supports(int F, int lanes, int precision) {
+  if (precision == ESIM_GRAM_F32C) return pick_c32(F, lanes, false) != nullptr;
+  return pick(F, lanes, false) != nullptr;
+}
+
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
                           int blocks_per_cu, hipStream_t s) {
-  (void)precision;
-  KernelFn fn = pick(F, lanes, f16);
+  KernelFn fn = precision == ESIM_GRAM_F32C ? pick_c32(F, lanes, f16) : pick(F, lanes, f16);
   if (!fn) return hipErrorInvalidValue;
   int64_t blocks = (a.max_groups + kWavesPerBlock - 1) / kWavesPerBlock;
   const int64_t cap = static_cast<int64_t>(256) * blocks_per_cu;

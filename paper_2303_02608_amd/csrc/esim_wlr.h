@@ -19,24 +19,24 @@ namespace esim {
 
 constexpr double kHalfLog2e = -0.72134752044448170368;  // -log2(e) / 2
 
-template <int F, bool F16>
+template <int F, bool F16, class Real = double>
 struct ItemGeom {
   static constexpr uint32_t ES = F16 ? 2u : 4u;
   __amdgpu_buffer_rsrc_t ry, rf;
   uint32_t HW, vcen_f, vcen_y;
   int W, H, T, r, tr, px, py, fc, tt, dt_lo, dt_hi;
   bool active;
-  double sf[F + 2];
-  double xcs[F];
-  double vx_step, vy_step;
+  Real sf[F + 2];
+  Real xcs[F];
+  Real vx_step, vy_step;
 };
 
 // Fills the geometry of the item at (pix, tt) of clip C.  f0/f1 are the frames
 // the buffer resources cover (a uniform frame's window, or the whole clip).
-template <int F, bool F16>
-__device__ __forceinline__ void make_geom(ItemGeom<F, F16>& g, const ClipDev& C, int64_t pix, int tt,
-                                          int f0, int f1, bool active) {
-  constexpr uint32_t ES = ItemGeom<F, F16>::ES;
+template <int F, bool F16, class Real>
+__device__ __forceinline__ void make_geom(ItemGeom<F, F16, Real>& g, const ClipDev& C, int64_t pix,
+                                          int tt, int f0, int f1, bool active) {
+  constexpr uint32_t ES = ItemGeom<F, F16, Real>::ES;
   g.W = C.W;
   g.H = C.H;
   g.T = C.T;
@@ -54,13 +54,12 @@ __device__ __forceinline__ void make_geom(ItemGeom<F, F16>& g, const ClipDev& C,
   g.vcen_f = (static_cast<uint32_t>(g.fc) * F * g.HW + static_cast<uint32_t>(pix)) * ES;
   g.vcen_y = (static_cast<uint32_t>(g.fc) * g.HW + static_cast<uint32_t>(pix)) * 4u;
 #pragma unroll
-  for (int d = 0; d < F + 2; ++d) g.sf[d] = C.sf[d];
+  for (int d = 0; d < F + 2; ++d) g.sf[d] = static_cast<Real>(C.sf[d]);
 #pragma unroll
   for (int f = 0; f < F; ++f)
-    g.xcs[f] = static_cast<double>(ld_feat<F16>(g.rf, g.vcen_f, f * g.HW * ES)) * g.sf[2 + f];
-  const double rinv = 1.0 / g.r;
-  g.vx_step = rinv * g.sf[0];
-  g.vy_step = rinv * g.sf[1];
+    g.xcs[f] = static_cast<Real>(ld_feat<F16>(g.rf, g.vcen_f, f * g.HW * ES)) * g.sf[2 + f];
+  g.vx_step = static_cast<Real>(C.sf[0] / g.r);
+  g.vy_step = static_cast<Real>(C.sf[1] / g.r);
   g.dt_lo = max(-g.tr, -tt);
   g.dt_hi = min(g.tr, g.T - 1 - tt);
 }
@@ -73,10 +72,12 @@ __device__ __forceinline__ void make_geom(ItemGeom<F, F16>& g, const ClipDev& C,
 //                                       padding row of an odd row count, whose
 //                                       (dt, dy) lie past the window
 //   pass_end(vx)                        after each column pass
-template <int F, int L, bool F16, class PassBegin, class Sample, class PassEnd>
-__device__ __forceinline__ void window_loop(const ItemGeom<F, F16>& g, int j, PassBegin&& pass_begin,
-                                            Sample&& sample, PassEnd&& pass_end) {
-  constexpr uint32_t ES = ItemGeom<F, F16>::ES;
+template <int F, int L, bool F16, class Real, class PassBegin, class Sample, class PassEnd>
+__device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int j,
+                                            PassBegin&& pass_begin, Sample&& sample,
+                                            PassEnd&& pass_end) {
+  constexpr uint32_t ES = ItemGeom<F, F16, Real>::ES;
+  constexpr Real K = static_cast<Real>(kHalfLog2e);
   const int r = g.r;
   const int nrows = (g.dt_hi - g.dt_lo + 1) * (2 * r + 1);
   const int npass = (2 * r + 1 + L - 1) / L;
@@ -84,8 +85,8 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16>& g, int j, Pa
     const int dx = -r + j + k * L;
     const int col = g.px + dx;
     const bool col_ok = g.active && dx <= r && col >= 0 && col < g.W;
-    const double vx = dx * g.vx_step;
-    const double kx = kHalfLog2e * vx * vx;
+    const Real vx = static_cast<Real>(dx) * g.vx_step;
+    const Real kx = K * vx * vx;
     pass_begin(vx);
     int ldt = g.dt_lo, ldy = -r;   // next row to load
     auto load_row = [&](float& yv, float (&fv)[F]) -> bool {
@@ -114,19 +115,19 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16>& g, int j, Pa
         cdy = -r;
         ++cdt;
       }
-      const double vy = static_cast<double>(dy) * g.vy_step;
-      double v[F];
-      double s0 = 0.0, s1 = 0.0;
+      const Real vy = static_cast<Real>(dy) * g.vy_step;
+      Real v[F];
+      Real s0 = 0, s1 = 0;
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        v[f] = fma(static_cast<double>(fv[f]), g.sf[2 + f], -g.xcs[f]);
+        v[f] = fma(static_cast<Real>(fv[f]), g.sf[2 + f], -g.xcs[f]);
         if (f & 1) s1 = fma(v[f], v[f], s1);
         else s0 = fma(v[f], v[f], s0);
       }
-      const double arg = fma(s0 + s1, kHalfLog2e, fma(kHalfLog2e * vy, vy, kx));
+      const Real arg = fma(s0 + s1, K, fma(K * vy, vy, kx));
       const float e = __builtin_amdgcn_exp2f(static_cast<float>(arg));
-      const double w = static_cast<double>(ok ? e : 0.0f);
-      sample(w, static_cast<double>(yv), v, vy, dx, dt, dy, ok);
+      const Real w = static_cast<Real>(ok ? e : 0.0f);
+      sample(w, static_cast<Real>(yv), v, vy, dx, dt, dy, ok);
     };
     // two rows per iteration in one basic block (an odd last row is used with
     // weight 0), so the scheduler can overlap the weight of one row with the
@@ -146,29 +147,29 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16>& g, int j, Pa
 
 // Normal equations of one item, accumulated per lane (Gram entries with a v_x
 // factor are folded once per column pass).
-template <int F>
+template <int F, class Real = double>
 struct Gram {
   static constexpr int NA = F * (F + 1) / 2;
-  double SW, A0y, g0, A0f[F];
-  double A0x, Axx, Axy, gx, Axf[F];
-  double Ayy, gy, Syy, Ayf[F], gf[F], Aff[NA];
-  double qW, qY, qG, qF[F];
+  Real SW, A0y, g0, A0f[F];
+  Real A0x, Axx, Axy, gx, Axf[F];
+  Real Ayy, gy, Syy, Ayf[F], gf[F], Aff[NA];
+  Real qW, qY, qG, qF[F];
 
   __device__ __forceinline__ void zero() {
-    SW = A0y = g0 = A0x = Axx = Axy = gx = Ayy = gy = Syy = 0.0;
+    SW = A0y = g0 = A0x = Axx = Axy = gx = Ayy = gy = Syy = 0;
 #pragma unroll
-    for (int f = 0; f < F; ++f) A0f[f] = Axf[f] = Ayf[f] = gf[f] = 0.0;
+    for (int f = 0; f < F; ++f) A0f[f] = Axf[f] = Ayf[f] = gf[f] = 0;
 #pragma unroll
-    for (int k = 0; k < NA; ++k) Aff[k] = 0.0;
+    for (int k = 0; k < NA; ++k) Aff[k] = 0;
   }
   __device__ __forceinline__ void pass_begin() {
-    qW = qY = qG = 0.0;
+    qW = qY = qG = 0;
 #pragma unroll
-    for (int f = 0; f < F; ++f) qF[f] = 0.0;
+    for (int f = 0; f < F; ++f) qF[f] = 0;
   }
-  __device__ __forceinline__ void add(double w, double yd, const double (&v)[F], double vy) {
-    const double wy = w * yd;
-    const double wvy = w * vy;
+  __device__ __forceinline__ void add(Real w, Real yd, const Real (&v)[F], Real vy) {
+    const Real wy = w * yd;
+    const Real wvy = w * vy;
     qW += w;
     qY += wvy;
     qG += wy;
@@ -178,7 +179,7 @@ struct Gram {
     int qq = 0;
 #pragma unroll
     for (int f = 0; f < F; ++f) {
-      const double wz = w * v[f];
+      const Real wz = w * v[f];
       qF[f] += wz;
       Ayf[f] = fma(wvy, v[f], Ayf[f]);
       gf[f] = fma(wz, yd, gf[f]);
@@ -189,7 +190,7 @@ struct Gram {
       }
     }
   }
-  __device__ __forceinline__ void pass_end(double vx) {
+  __device__ __forceinline__ void pass_end(Real vx) {
     SW += qW;
     A0y += qY;
     g0 += qG;
@@ -229,45 +230,176 @@ struct Gram {
   }
 };
 
+// Neumaier-compensated accumulation: (hi, lo) += x.
+__device__ __forceinline__ void neumaier(float& hi, float& lo, float x) {
+  const float t = hi + x;
+  lo += fabsf(hi) >= fabsf(x) ? (hi - t) + x : (x - t) + hi;
+  hi = t;
+}
+
+// FP32 normal equations with block-compensated sums: every sample updates
+// plain FP32 partials of the current column pass (a block of 2tr+1 times
+// 2r+1 samples); at the end of the pass each partial is added to a
+// Neumaier-compensated (hi, lo) total, and lane groups merge their totals
+// with error-free two-sums.  Values are read back as hi + lo.
+template <int F>
+struct GramC {
+  static constexpr int NA = F * (F + 1) / 2;
+  static constexpr int NQ = F + 3;             // qW, qY, qG, qF[F]
+  static constexpr int ND = 3 + 2 * F + NA;    // Ayy, gy, Syy, Ayf[F], gf[F], Aff[NA]
+  static constexpr int NT = 2 * NQ + 1 + ND;   // q totals, x folds, Axx, directs
+  float q[NQ], d[ND];
+  float hi[NT], lo[NT];
+
+  __device__ __forceinline__ void zero() {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) hi[k] = lo[k] = 0.0f;
+  }
+  __device__ __forceinline__ void pass_begin() {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q[k] = 0.0f;
+#pragma unroll
+    for (int k = 0; k < ND; ++k) d[k] = 0.0f;
+  }
+  __device__ __forceinline__ void add(float w, float yd, const float (&v)[F], float vy) {
+    const float wy = w * yd;
+    const float wvy = w * vy;
+    q[0] += w;
+    q[1] += wvy;
+    q[2] += wy;
+    d[0] = fmaf(wvy, vy, d[0]);
+    d[1] = fmaf(wy, vy, d[1]);
+    d[2] = fmaf(wy, yd, d[2]);
+    int qq = 0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const float wz = w * v[f];
+      q[3 + f] += wz;
+      d[3 + f] = fmaf(wvy, v[f], d[3 + f]);
+      d[3 + F + f] = fmaf(wz, yd, d[3 + F + f]);
+#pragma unroll
+      for (int e = f; e < F; ++e) {
+        d[3 + 2 * F + qq] = fmaf(wz, v[e], d[3 + 2 * F + qq]);
+        ++qq;
+      }
+    }
+  }
+  __device__ __forceinline__ void pass_end(float vx) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) {
+      neumaier(hi[k], lo[k], q[k]);
+      neumaier(hi[NQ + k], lo[NQ + k], vx * q[k]);
+    }
+    neumaier(hi[2 * NQ], lo[2 * NQ], vx * vx * q[0]);
+#pragma unroll
+    for (int k = 0; k < ND; ++k) neumaier(hi[2 * NQ + 1 + k], lo[2 * NQ + 1 + k], d[k]);
+  }
+  template <int L>
+  __device__ __forceinline__ void lane_sum() {
+#pragma unroll
+    for (int k = 0; k < NT; ++k) {
+      float h = hi[k], l = lo[k];
+      auto step = [&](float h2, float l2) {
+        const float s = h + h2;
+        const float bb = s - h;
+        const float err = (h - (s - bb)) + (h2 - bb);
+        h = s;
+        l = l + l2 + err;
+      };
+      if constexpr (L >= 2) step(dpp_f<0xB1>(h), dpp_f<0xB1>(l));
+      if constexpr (L >= 4) step(dpp_f<0x4E>(h), dpp_f<0x4E>(l));
+      if constexpr (L >= 8) step(dpp_f<0x141>(h), dpp_f<0x141>(l));
+      if constexpr (L >= 16) step(dpp_f<0x140>(h), dpp_f<0x140>(l));
+      hi[k] = h;
+      lo[k] = l;
+    }
+  }
+  // Totals in the Gram layout, as Real (hi + lo evaluated in Real).
+  template <class Real>
+  __device__ __forceinline__ void values(Gram<F, Real>& G) const {
+    auto v = [&](int k) { return static_cast<Real>(hi[k]) + static_cast<Real>(lo[k]); };
+    G.SW = v(0);
+    G.A0y = v(1);
+    G.g0 = v(2);
+    G.A0x = v(NQ + 0);
+    G.Axy = v(NQ + 1);
+    G.gx = v(NQ + 2);
+    G.Axx = v(2 * NQ);
+    G.Ayy = v(2 * NQ + 1);
+    G.gy = v(2 * NQ + 2);
+    G.Syy = v(2 * NQ + 3);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      G.A0f[f] = v(3 + f);
+      G.Axf[f] = v(NQ + 3 + f);
+      G.Ayf[f] = v(2 * NQ + 4 + f);
+      G.gf[f] = v(2 * NQ + 4 + F + f);
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k) G.Aff[k] = v(2 * NQ + 4 + 2 * F + k);
+  }
+};
+
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
 // Solves L L^T x = b with the packed factor.
-template <int P>
-__device__ __forceinline__ void chol_solve(const double (&M)[P * (P + 1) / 2], const double (&b)[P],
-                                           double (&x)[P]) {
+template <int P, class Real>
+__device__ __forceinline__ void chol_solve(const Real (&M)[P * (P + 1) / 2], const Real (&b)[P],
+                                           Real (&x)[P]) {
 #pragma unroll
   for (int i = 0; i < P; ++i) {
-    double v = b[i];
+    Real v = b[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) v -= M[tri(i, k)] * x[k];
     x[i] = v / M[tri(i, i)];
   }
 #pragma unroll
   for (int i = P - 1; i >= 0; --i) {
-    double v = x[i];
+    Real v = x[i];
 #pragma unroll
     for (int k = i + 1; k < P; ++k) v -= M[tri(k, i)] * x[k];
     x[i] = v / M[tri(i, i)];
   }
 }
 
+// In-place packed Cholesky; a non-positive pivot yields NaN.
+template <int P, class Real>
+__device__ __forceinline__ void cholesky_inplace(Real (&M)[P * (P + 1) / 2]) {
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    Real s = M[tri(c, c)];
+#pragma unroll
+    for (int k = 0; k < c; ++k) s -= M[tri(c, k)] * M[tri(c, k)];
+    const Real d = s > Real(0) ? sqrt(s) : static_cast<Real>(__builtin_nan(""));
+    const Real id = Real(1) / d;
+    M[tri(c, c)] = d;
+#pragma unroll
+    for (int i = c + 1; i < P; ++i) {
+      Real v = M[tri(i, c)];
+#pragma unroll
+      for (int k = 0; k < c; ++k) v -= M[tri(i, k)] * M[tri(c, k)];
+      M[tri(i, c)] = v * id;
+    }
+  }
+}
 
 // Assembles the W-normalised system in scaled units (unknowns alpha, beta_x,
 // beta_y, beta_f..), adds the scaled ridge, factors it in place (packed lower
-// Cholesky) and solves for theta.  Returns 1/W.  dmin/dmax are the extreme
-// diagonal entries of the factor.
-template <int F>
-__device__ __forceinline__ double gram_solve(const Gram<F>& G, const ClipDev& C,
-                                             double (&M)[(F + 3) * (F + 4) / 2], double (&rhs)[F + 3],
-                                             double (&th)[F + 3], double& dmin, double& dmax) {
+// Cholesky) and solves for theta.  Returns 1/W.  anorm1 receives the 1-norm of
+// the assembled matrix (for the condition estimate).
+template <int F, class Real>
+__device__ __forceinline__ Real gram_solve(const Gram<F, Real>& G, const ClipDev& C,
+                                           Real (&M)[(F + 3) * (F + 4) / 2], Real (&rhs)[F + 3],
+                                           Real (&th)[F + 3], Real& anorm1) {
   constexpr int P = F + 3;
-  const double iW = 1.0 / G.SW;
-  M[tri(0, 0)] = 1.0;
+  const Real iW = Real(1) / G.SW;
+  const Real lam = static_cast<Real>(C.ridge);
+  M[tri(0, 0)] = Real(1);
   M[tri(1, 0)] = G.A0x * iW;
   M[tri(2, 0)] = G.A0y * iW;
-  M[tri(1, 1)] = G.Axx * iW + C.ridge * C.c2[0];
+  M[tri(1, 1)] = G.Axx * iW + lam * static_cast<Real>(C.c2[0]);
   M[tri(2, 1)] = G.Axy * iW;
-  M[tri(2, 2)] = G.Ayy * iW + C.ridge * C.c2[1];
+  M[tri(2, 2)] = G.Ayy * iW + lam * static_cast<Real>(C.c2[1]);
   rhs[0] = G.g0 * iW;
   rhs[1] = G.gx * iW;
   rhs[2] = G.gy * iW;
@@ -281,33 +413,85 @@ __device__ __forceinline__ double gram_solve(const Gram<F>& G, const ClipDev& C,
       rhs[3 + f] = G.gf[f] * iW;
 #pragma unroll
       for (int e = f; e < F; ++e) {
-        M[tri(3 + e, 3 + f)] = G.Aff[q] * iW + (e == f ? C.ridge * C.c2[2 + f] : 0.0);
+        M[tri(3 + e, 3 + f)] = G.Aff[q] * iW + (e == f ? lam * static_cast<Real>(C.c2[2 + f]) : Real(0));
         ++q;
       }
     }
   }
-  dmin = 1e300;
-  dmax = 0.0;
+  anorm1 = 0;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
-    double s = M[tri(c, c)];
+    Real cs = 0;
 #pragma unroll
-    for (int k = 0; k < c; ++k) s -= M[tri(c, k)] * M[tri(c, k)];
-    const double d = s > 0.0 ? sqrt(s) : __builtin_nan("");
-    const double id = 1.0 / d;
-    M[tri(c, c)] = d;
-    dmin = fmin(dmin, d);
-    dmax = fmax(dmax, d);
-#pragma unroll
-    for (int i = c + 1; i < P; ++i) {
-      double v = M[tri(i, c)];
-#pragma unroll
-      for (int k = 0; k < c; ++k) v -= M[tri(i, k)] * M[tri(c, k)];
-      M[tri(i, c)] = v * id;
-    }
+    for (int i = 0; i < P; ++i) cs += fabs(i >= c ? M[tri(i, c)] : M[tri(c, i)]);
+    anorm1 = fmax(anorm1, cs);
   }
-  chol_solve<P>(M, rhs, th);
+  cholesky_inplace<P, Real>(M);
+  chol_solve<P, Real>(M, rhs, th);
   return iW;
+}
+
+// Estimate of ||A^{-1}||_1 for a symmetric positive definite A from its
+// Cholesky factor, after Hager (1984) with Higham's refinements (1988, the
+// scheme of LAPACK's xLACN2): power-like steps on sign vectors, at most five
+// solves with unit vectors, then an extra test vector with alternating signs.
+// kappa_1 is estimated as ||A||_1 times this; the estimate never exceeds the
+// true value.
+template <int P, class Real>
+__device__ __forceinline__ Real hager_inv_norm1(const Real (&M)[P * (P + 1) / 2]) {
+  Real b[P], x[P], z[P], xi[P];
+  auto norm1 = [&](const Real (&v)[P]) {
+    Real s = 0;
+#pragma unroll
+    for (int i = 0; i < P; ++i) s += fabs(v[i]);
+    return s;
+  };
+  auto argmax_abs = [&](const Real (&v)[P]) {
+    int jm = 0;
+    Real m = fabs(v[0]);
+#pragma unroll
+    for (int i = 1; i < P; ++i)
+      if (fabs(v[i]) > m) {
+        m = fabs(v[i]);
+        jm = i;
+      }
+    return jm;
+  };
+#pragma unroll
+  for (int i = 0; i < P; ++i) b[i] = Real(1) / P;
+  chol_solve<P, Real>(M, b, x);
+  Real est = norm1(x);
+#pragma unroll
+  for (int i = 0; i < P; ++i) xi[i] = x[i] >= Real(0) ? Real(1) : Real(-1);
+  chol_solve<P, Real>(M, xi, z);
+  int j = argmax_abs(z);
+#pragma unroll 1
+  for (int iter = 0; iter < 4; ++iter) {
+#pragma unroll
+    for (int i = 0; i < P; ++i) b[i] = i == j ? Real(1) : Real(0);
+    chol_solve<P, Real>(M, b, x);
+    const Real old = est;
+    est = fmax(est, norm1(x));
+    bool same = true;
+#pragma unroll
+    for (int i = 0; i < P; ++i) {
+      const Real sgn = x[i] >= Real(0) ? Real(1) : Real(-1);
+      same = same && sgn == xi[i];
+      xi[i] = sgn;
+    }
+    if (same || !(est > old)) break;
+    chol_solve<P, Real>(M, xi, z);
+    const int jn = argmax_abs(z);
+    if (fabs(z[jn]) == fabs(z[j])) break;
+    j = jn;
+  }
+  // alternating-sign test vector
+#pragma unroll
+  for (int i = 0; i < P; ++i)
+    b[i] = (i & 1 ? Real(-1) : Real(1)) * (Real(1) + static_cast<Real>(i) / static_cast<Real>(P > 1 ? P - 1 : 1));
+  chol_solve<P, Real>(M, b, x);
+  est = fmax(est, Real(2) * norm1(x) / (Real(3) * P));
+  return est;
 }
 
 }  // namespace esim
