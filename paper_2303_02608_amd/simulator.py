@@ -93,3 +93,54 @@ class Simulator:
 
     def events(self):
         return self.ev.host()
+
+
+class BatchSimulator:
+    """The thresholded conversion of many clips of uneven size and length in
+    one plan: every step launches one threshold, one work-list regression and
+    one event call over all clips still running (a clip of length T takes part
+    in steps 0..T-1).  Events carry their clip index."""
+
+    def __init__(self, ys, feats, params, capacity: Optional[int] = None):
+        self.plan = B.Plan(list(ys), list(feats), list(params))
+        dev = feats[0].device
+        self.T = max(int(f.shape[0]) for f in feats)
+        self.npix = self.plan.npix
+        self.n_out = max(self.plan.npix, self.plan.wl_capacity)
+        self.dl = torch.empty(self.npix, dtype=torch.float32, device=dev)
+        self.worklist = torch.empty(self.plan.wl_capacity, dtype=torch.int64, device=dev)
+        self.count = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.alpha = torch.empty(self.n_out, dtype=torch.float32, device=dev)
+        self.beta = torch.empty((self.plan.D, self.n_out), dtype=torch.float32, device=dev)
+        if capacity is None:
+            capacity = min(sum(int(f.shape[0]) * f.shape[2] * f.shape[3] for f in feats), 1 << 27)
+        self.ev = B.Events(capacity, dev, with_clip=True)
+
+    def enqueue(self):
+        p, n = self.plan, self.n_out
+        self.ev.count.zero_()
+        B.regress(p, 0, None, None, n, self.alpha, self.beta)
+        B.events(p, 0, B.INIT, None, alpha=self.alpha, beta=self.beta, n_out=n)
+        for t in range(1, self.T):
+            B.threshold(p, t, self.dl, self.worklist, self.count)
+            B.regress(p, t, self.worklist, self.count, n, self.alpha, self.beta)
+            B.events(p, t, B.THRESHOLDED, self.ev, worklist=self.worklist, count=self.count,
+                     dl=self.dl, alpha=self.alpha, beta=self.beta, n_out=n)
+
+    def capture(self):
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(s):
+            self.enqueue()
+        torch.cuda.current_stream().wait_stream(s)
+        torch.cuda.synchronize()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.enqueue()
+        self.graph = g
+        return g
+
+    def run(self):
+        self.enqueue()
+        torch.cuda.synchronize()
+        return self.ev.host()

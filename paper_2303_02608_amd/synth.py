@@ -233,48 +233,54 @@ class _Scene:
         self.fine_bump = _ValueNoise(s.seed, 4, 6.0)
 
     @staticmethod
-    def _reflect(p0: float, v: float, t: float, lo: float, hi: float) -> float:
+    def _reflect(p0: float, v: float, t: torch.Tensor, lo: float, hi: float):
+        """Position and velocity sign of a point bouncing between lo and hi."""
         span = hi - lo
         if span <= 0:
-            return lo, 1.0
-        x = (p0 - lo + v * t) % (2 * span)
-        return lo + (x if x <= span else 2 * span - x), (1.0 if x <= span else -1.0)
+            return torch.full_like(t, lo), torch.ones_like(t)
+        x = torch.remainder(p0 - lo + v * t, 2 * span)
+        fwd = x <= span
+        return lo + torch.where(fwd, x, 2 * span - x), torch.where(fwd, 1.0, -1.0).to(t.dtype)
 
-    def disc_state(self, k: int, t: float):
+    def disc_states(self, k: int, tf: torch.Tensor):
+        """Centre, velocity and angle of disc k at frames tf ([nf] float64)."""
         d = self.discs[k]
         s = self.s
         R = d["R"]
-        cx, sx = self._reflect(d["c0"][0], d["v"][0], t, R, s.W - R)
-        cy, sy = self._reflect(d["c0"][1], d["v"][1], t, R, s.H - R)
-        return cx, cy, d["v"][0] * sx, d["v"][1] * sy, d["th0"] + d["om"] * t
+        cx, sx = self._reflect(d["c0"][0], d["v"][0], tf, R, s.W - R)
+        cy, sy = self._reflect(d["c0"][1], d["v"][1], tf, R, s.H - R)
+        return cx, cy, d["v"][0] * sx, d["v"][1] * sy, d["th0"] + d["om"] * tf
 
-    def shade(self, t: int, x: torch.Tensor, y: torch.Tensor):
+    def shade(self, tf: torch.Tensor, x: torch.Tensor, y: torch.Tensor):
         """Surface attributes at continuous image positions (pixel centres at
-        integer + 0.5).  Returns dict of tensors shaped like x."""
+        integer + 0.5).  x, y: [nf, n] positions in the frames tf ([nf]).
+        Returns a dict of flattened [nf * n] tensors."""
         s = self.s
+        nf, n = x.shape
+        X, Y = x.reshape(-1), y.reshape(-1)
         # background
-        alb = [0.3 + 0.4 * f.octaves(x, y) for f in self.bg_alb]
+        alb = [0.3 + 0.4 * f.octaves(X, Y) for f in self.bg_alb]
         e = 0.5
         h = lambda xx, yy: s.bump_amp * self.bump(xx, yy)
-        hx = (h(x + e, y) - h(x - e, y)) / (2 * e)
-        hy = (h(x, y + e) - h(x, y - e)) / (2 * e)
-        nx, ny, nz = -hx, -hy, torch.ones_like(x)
-        depth = 10.0 + 0.01 * y + 0.5 * h(x, y)
-        mx = torch.zeros_like(x)
-        my = torch.zeros_like(x)
-        alb = list(alb)
+        hx = (h(X + e, Y) - h(X - e, Y)) / (2 * e)
+        hy = (h(X, Y + e) - h(X, Y - e)) / (2 * e)
+        nx, ny, nz = -hx, -hy, torch.ones_like(X)
+        depth = 10.0 + 0.01 * Y + 0.5 * h(X, Y)
+        mx = torch.zeros_like(X)
+        my = torch.zeros_like(X)
         for k, d in enumerate(self.discs):
-            cx, cy, vx, vy, th = self.disc_state(k, float(t))
+            cx, cy, vx, vy, th = [v.to(torch.float32) for v in self.disc_states(k, tf)]
             R = d["R"]
-            inside = ((x - cx) ** 2 + (y - cy) ** 2) < R * R
-            idx = torch.nonzero(inside, as_tuple=True)[0]
+            dX = x - cx[:, None]
+            dY = y - cy[:, None]
+            idx = torch.nonzero(((dX * dX + dY * dY) < R * R).reshape(-1), as_tuple=True)[0]
             if idx.numel() == 0:
                 continue
-            xs, ys = x[idx], y[idx]
-            dx = xs - cx
-            dy = ys - cy
+            fi = idx // n
+            dx = dX.reshape(-1)[idx]
+            dy = dY.reshape(-1)[idx]
             rho2 = (dx * dx + dy * dy) / (R * R)
-            c, sn = math.cos(-th), math.sin(-th)
+            c, sn = torch.cos(-th)[fi], torch.sin(-th)[fi]
             qx = c * dx - sn * dy + 1000.0
             qy = sn * dx + c * dy + 1000.0
             for ch in range(3):
@@ -285,15 +291,15 @@ class _Scene:
             ny = ny.index_put((idx,), 0.8 * dy / R)
             nz = nz.index_put((idx,), dome)
             depth = depth.index_put((idx,), d["depth"] - 2.0 * torch.sqrt(torch.clamp(1.0 - rho2, min=0.0)))
-            mx = mx.index_put((idx,), vx - d["om"] * dy)
-            my = my.index_put((idx,), vy + d["om"] * dx)
+            mx = mx.index_put((idx,), vx[fi] - d["om"] * dy)
+            my = my.index_put((idx,), vy[fi] + d["om"] * dx)
         inv = torch.rsqrt(nx * nx + ny * ny + nz * nz)
         nx, ny, nz = nx * inv, ny * inv, nz * inv
         lx, ly, lz = self.light
         ndl = torch.clamp(nx * lx + ny * ly + nz * lz, min=0.05)
         lum = 0.2126 * alb[0] + 0.7152 * alb[1] + 0.0722 * alb[2]
-        G = 0.2 + 0.8 * (0.5 + 0.5 * torch.sin(self.g_a * x / s.W * math.pi
-                                                + self.g_b * y / s.H * math.pi + self.g_ph))
+        G = 0.2 + 0.8 * (0.5 + 0.5 * torch.sin(self.g_a * X / s.W * math.pi
+                                                + self.g_b * Y / s.H * math.pi + self.g_ph))
         E = lum * ndl * G
         out = dict(nx=nx, ny=ny, nz=nz, ar=alb[0], ag=alb[1], ab=alb[2],
                    depth=depth / self.depth_bound, mx=mx / s.motion_scale,
@@ -302,8 +308,8 @@ class _Scene:
             # octahedral encodings of the geometric and a bump-perturbed normal
             out["on0"], out["on1"] = _octa(nx, ny, nz)
             fb = lambda xx, yy: 2.0 * self.fine_bump(xx, yy)
-            sx = (fb(x + e, y) - fb(x - e, y)) / (2 * e)
-            sy = (fb(x, y + e) - fb(x, y - e)) / (2 * e)
+            sx = (fb(X + e, Y) - fb(X - e, Y)) / (2 * e)
+            sy = (fb(X, Y + e) - fb(X, Y - e)) / (2 * e)
             snx, sny, snz = nx - 0.3 * sx, ny - 0.3 * sy, nz
             inv = torch.rsqrt(snx * snx + sny * sny + snz * snz)
             out["os0"], out["os1"] = _octa(snx * inv, sny * inv, snz * inv)
@@ -359,36 +365,43 @@ def make_clip(spec: ClipSpec, device="cpu", frames: Optional[Sequence[int]] = No
     py = pyi.to(torch.float32)
     px = pxi.to(torch.float32)
     HWfull = s.H * s.W
-    # chunk pixels so one frame's samples stay within a modest working set
-    chunk = max(1, (1 << 22) // max(1, s.spp))
-    for ti, t in enumerate(frames):
-        accE = torch.empty(HW, dtype=torch.float32, device=dev)
-        accV = torch.empty(HW, dtype=torch.float32, device=dev)
-        accF = torch.empty((s.F, HW), dtype=torch.float32, device=dev)
-        for c0 in range(0, HW, chunk):
-            c1 = min(HW, c0 + chunk)
+    # Work in chunks of whole frames (or of pixels of one frame when a frame
+    # alone is large) so each tensor op covers up to `budget` samples.
+    budget = (1 << 25) if dev.type == "cuda" else (1 << 21)
+    per_frame = HW * s.spp
+    if per_frame <= budget:
+        fchunk, pchunk = max(1, budget // per_frame), HW
+    else:
+        fchunk, pchunk = 1, max(1, budget // s.spp)
+    sidx = torch.arange(s.spp, dtype=torch.int64, device=dev)
+    for f0 in range(0, T, fchunk):
+        fsel = frames[f0:f0 + fchunk]
+        nf = len(fsel)
+        tt = torch.tensor(fsel, dtype=torch.int64, device=dev)
+        tf = tt.to(torch.float64)
+        for c0 in range(0, HW, pchunk):
+            c1 = min(HW, c0 + pchunk)
             n = c1 - c0
-            base = ((t * HWfull + pix[c0:c1]) * s.spp).unsqueeze(1) + \
-                torch.arange(s.spp, dtype=torch.int64, device=dev).unsqueeze(0)
+            # sample keys: ((t * HWfull + pixel) * spp + sample)
+            base = (((tt[:, None] * HWfull + pix[None, c0:c1]) * s.spp)[:, :, None]
+                    + sidx[None, None, :])                       # [nf, n, spp]
             jx = _uniform(s.seed, 1, base)
             jy = _uniform(s.seed, 2, base)
-            xs = (px[c0:c1].unsqueeze(1) + jx).reshape(-1)
-            ys = (py[c0:c1].unsqueeze(1) + jy).reshape(-1)
-            a = scene.shade(t, xs, ys)
+            xs = (px[None, c0:c1, None] + jx).reshape(nf, n * s.spp)
+            ys = (py[None, c0:c1, None] + jy).reshape(nf, n * s.spp)
+            a = scene.shade(tf, xs, ys)
             un = _uniform(s.seed, 3, base).reshape(-1)
             X = -torch.log1p(-un)                    # unit exponential = Gamma(k=1)
-            Es = (a["E"] * X).reshape(n, s.spp)
-            m = Es.mean(dim=1)
-            accE[c0:c1] = m
+            Es = (a["E"] * X).reshape(nf, n, s.spp)
+            m = Es.mean(dim=2)
+            E[f0:f0 + nf].view(nf, HW)[:, c0:c1] = m
             if s.spp > 1:
-                accV[c0:c1] = ((Es - m.unsqueeze(1)) ** 2).sum(dim=1) / (s.spp - 1)
+                V[f0:f0 + nf].view(nf, HW)[:, c0:c1] = ((Es - m[:, :, None]) ** 2).sum(dim=2) / (s.spp - 1)
             else:
-                accV[c0:c1] = 0.0
+                V[f0:f0 + nf].view(nf, HW)[:, c0:c1] = 0.0
             for f, name in enumerate(chans):
-                accF[f, c0:c1] = a[name].reshape(n, s.spp).mean(dim=1)
-        E[ti] = accE.reshape(ch, cw)
-        V[ti] = accV.reshape(ch, cw)
-        feat[ti] = accF.reshape(s.F, ch, cw).to(fdt)
+                feat[f0:f0 + nf, f].view(nf, HW)[:, c0:c1] = \
+                    a[name].reshape(nf, n, s.spp).mean(dim=2).to(fdt)
     return dict(E=E, var=V, feat=feat, spec=s)
 
 
