@@ -1,0 +1,206 @@
+"""Parity at the full workload sizes, in the launch configuration the benchmark
+times (autotuned schedule), on outputs the oracle can compute one by one:
+sampled pixels' whole event histories, sampled regressions, sampled adjoint
+items, and a finite-difference check of the full differentiation loss."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2303_02608_amd import autotune
+from paper_2303_02608_amd import binding as B
+from paper_2303_02608_amd import synth
+from paper_2303_02608_amd.autograd import wlr_alpha
+from paper_2303_02608_amd.simulator import Simulator
+from parity_util import MODE_ID, compare_events, say
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def dvs():
+    cfg = synth.config_spec(1)
+    say("generate DVS 640x480x120 on the GPU")
+    d = synth.make_clip(cfg["spec"], device="cuda")
+    E, feat = d["E"], d["feat"]
+    y = B.log_brightness(E)
+    torch.cuda.synchronize()
+    return dict(cfg=cfg, E=E, feat=feat, y=y, En=E.cpu().numpy(), fn=feat.cpu().numpy())
+
+
+def _oracle_clip(d):
+    if "oc" not in d:
+        d["oc"] = oracle.Clip(oracle.log_brightness(d["En"]), d["fn"])
+    return d["oc"]
+
+
+@pytest.mark.parametrize("mode", ["thresholded", "exhaustive", "raw"])
+def test_dvs_events_on_sampled_pixels(dvs, mode):
+    cfg = dvs["cfg"]
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"])
+    sim = Simulator(dvs["y"], dvs["feat"], p)
+    sched = autotune.tune(sim.plan)
+    say(f"DVS {mode}, schedule {sched}")
+    gpu = sim.run(mode)
+    T, F, H, W = dvs["fn"].shape
+    rng = np.random.default_rng(11)
+    # random pixels, and pixels that fire (so moving surfaces are covered)
+    fired = np.unique(gpu["y"].astype(np.int64) * W + gpu["x"])
+    pix = np.unique(np.concatenate([rng.choice(H * W, 48, replace=False),
+                                    rng.choice(fired, min(48, fired.size), replace=False)]))
+    orc = oracle.run(_oracle_clip(dvs), oracle.Params(p.r, p.tr, p.C), MODE_ID[mode], pixels=pix,
+                     want_dl=True)
+    n, exc, fails = compare_events(gpu, orc, W, p.C, 1e-4, pixels=pix)
+    say(f"DVS {mode}: {n} sampled pixels, {orc['count']} oracle events, excused {exc}")
+    assert not fails, fails[:5]
+    assert exc <= 2
+    assert orc["count"] > 0
+
+
+def test_dvs_sampled_regressions(dvs):
+    cfg = dvs["cfg"]
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"])
+    plan = B.Plan([dvs["y"]], [dvs["feat"]], [p])
+    HW = plan.npix
+    a = torch.empty(HW, device="cuda")
+    b = torch.empty((plan.D, HW), device="cuda")
+    K = torch.empty(HW, device="cuda")
+    rng = np.random.default_rng(3)
+    for t in (0, 57, 119):
+        say(f"DVS dense regression t={t}")
+        B.regress(plan, t, None, None, HW, a, b, None, K)
+        torch.cuda.synchronize()
+        pix = rng.choice(HW, 200, replace=False)
+        ref = oracle.regress_items(_oracle_clip(dvs), oracle.Params(p.r, p.tr, p.C), t * HW + pix)
+        th = ref["theta"]
+        ea = np.abs(a.cpu().numpy()[pix] - th[:, 0]) / np.maximum(1, np.abs(th[:, 0]))
+        eb = np.abs(b.cpu().numpy()[:, pix].T - th[:, 1:]) / np.maximum(1, np.abs(th[:, 1:]))
+        say(f"t={t}: alpha {ea.max():.2e} beta {eb.max():.2e}")
+        assert ea.max() <= 1e-4 and eb.max() <= 1e-4
+
+
+@pytest.fixture(scope="module")
+def diff_clip():
+    cfg = synth.config_spec(3)
+    say("generate differentiation clip 640x480x60 on the GPU")
+    d = synth.make_clip(cfg["spec"], device="cuda")
+    y = B.log_brightness(d["E"])
+    torch.cuda.synchronize()
+    return dict(cfg=cfg, E=d["E"], feat=d["feat"], y=y)
+
+
+def _loss_items(dc):
+    """Items of the differentiation loss: every regression of the thresholded
+    forward pass (all pixels at frame 0, then one per event), with, for each
+    event, the index of the same pixel's previous regression."""
+    cfg = dc["cfg"]
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"])
+    ev = Simulator(dc["y"], dc["feat"], p).run("thresholded")
+    T, F, H, W = dc["feat"].shape
+    HW = H * W
+    pix_ev = ev["y"].astype(np.int64) * W + ev["x"]
+    t_ev = ev["t"].astype(np.int64)
+    items = np.concatenate([np.arange(HW, dtype=np.int64), (t_ev << 44) | pix_ev])
+    last = np.arange(HW, dtype=np.int64)          # index of each pixel's latest regression
+    prev = np.empty(pix_ev.size, np.int64)
+    for k, q in enumerate(pix_ev):                # events are in (t, py, px) order
+        prev[k] = last[q]
+        last[q] = HW + k
+    return items, prev, p
+
+
+def _loss(alpha, prev, HW):
+    d = alpha[HW:] - alpha[torch.from_numpy(prev).cuda()]
+    return (d.double() ** 2).sum()
+
+
+def test_diff_loss_gradient_full_size(diff_clip):
+    """Full differentiation loss sum over flagged regressions of
+    (alpha_t - alpha_ref)^2 with the flag set frozen: the adjoint's bandwidth
+    gradient against central finite differences of the same GPU forward."""
+    dc = diff_clip
+    items, prev, p = _loss_items(dc)
+    HW = dc["feat"].shape[2] * dc["feat"].shape[3]
+    say(f"diff loss: {items.size} regressions")
+    it = torch.from_numpy(items).cuda()
+    b = torch.ones(dc["feat"].shape[1] + 2, dtype=torch.float64, requires_grad=True)
+    y = dc["y"].clone().requires_grad_(True)
+    alpha = wlr_alpha(y, b, dc["feat"], it, p.r, p.tr, C=p.C)
+    loss = _loss(alpha, prev, HW)
+    loss.backward()
+    g = b.grad.numpy()
+    assert np.all(np.isfinite(g)) and torch.isfinite(y.grad).all()
+    h = 1e-3
+    for j in (2, 5, 8):
+        vals = []
+        for sgn in (1, -1):
+            bb = torch.ones_like(b).detach()
+            bb[j] += sgn * h
+            a2 = wlr_alpha(dc["y"], bb, dc["feat"], it, p.r, p.tr, C=p.C)
+            vals.append(float(_loss(a2, prev, HW)))
+        fd = (vals[0] - vals[1]) / (2 * h)
+        say(f"dL/db_{j}: adjoint {g[j]:.6e} central FD {fd:.6e}")
+        assert g[j] == pytest.approx(fd, rel=2e-3, abs=1e-6 * abs(float(loss)))
+
+
+def test_diff_sampled_adjoint_items(diff_clip):
+    """The adjoint at full size with the upstream gradient on a sample of the
+    loss's regressions only, against the oracle's adjoint of those items."""
+    dc = diff_clip
+    items, prev, p = _loss_items(dc)
+    rng = np.random.default_rng(5)
+    sel = rng.choice(items.size, 24, replace=False)
+    ga = np.zeros(items.size)
+    ga[sel] = rng.standard_normal(sel.size)
+    T, F, H, W = dc["feat"].shape
+    HW = H * W
+    y = dc["y"].clone().requires_grad_(True)
+    b = torch.ones(F + 2, dtype=torch.float64, requires_grad=True)
+    alpha = wlr_alpha(y, b, dc["feat"], torch.from_numpy(items).cuda(), p.r, p.tr, C=p.C)
+    (alpha * torch.from_numpy(ga).float().cuda()).sum().backward()
+    torch.cuda.synchronize()
+    En, fn = dc["E"].cpu().numpy(), dc["feat"].cpu().numpy()
+    clip = oracle.Clip(oracle.log_brightness(En), fn)
+    flat = (items[sel] >> 44) * HW + (items[sel] & 0xFFFFFFFF)
+    ref_y, ref_b, fails = oracle.backward(clip, oracle.Params(p.r, p.tr, p.C), flat, ga[sel])
+    assert fails == 0
+    gy = y.grad.cpu().numpy()
+    nz = np.nonzero(ref_y)
+    ey = np.abs(gy[nz] - ref_y[nz]).max() / np.abs(ref_y).max()
+    eb = np.abs(b.grad.numpy() - ref_b).max() / np.abs(ref_b).max()
+    say(f"sampled adjoint: g_y {ey:.2e}, g_b {eb:.2e}")
+    assert ey <= 1e-4 and eb <= 1e-4
+    # nothing outside the sampled items' windows
+    mask = np.ones_like(gy, bool)
+    mask[nz] = False
+    assert np.abs(gy[mask]).max() <= 1e-6 * np.abs(ref_y).max()
+
+
+def test_precision_workload_sampled():
+    """The precision workload's shape (1920x1080, F = 10 FP16 features, r = 10,
+    tr = 2) on its first 12 frames: FP64 path and compensated FP32 path at
+    sampled pixels against the oracle on the same FP16 values."""
+    cfg = synth.config_spec(4)
+    say("generate precision workload, 12 frames, on the GPU")
+    d = synth.make_clip(cfg["spec"], device="cuda", frames=range(12))
+    y = B.log_brightness(d["E"])
+    feat = d["feat"]
+    assert feat.dtype == torch.float16
+    clip = oracle.Clip(oracle.log_brightness(d["E"].cpu().numpy()), feat.cpu().numpy())
+    HW = 1920 * 1080
+    rng = np.random.default_rng(8)
+    pix = rng.choice(HW, 96, replace=False)
+    ref = oracle.regress_items(clip, oracle.Params(cfg["r"], cfg["tr"], cfg["C"]), 6 * HW + pix)
+    th = ref["theta"]
+    for prec in (B.GRAM_F64, B.GRAM_F32C):
+        p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"], precision=prec, kappa_fp64=1e6)
+        plan = B.Plan([y], [feat], [p])
+        a = torch.empty(HW, device="cuda")
+        b = torch.empty((plan.D, HW), device="cuda")
+        K = torch.empty(HW, device="cuda")
+        B.regress(plan, 6, None, None, HW, a, b, None, K)
+        torch.cuda.synchronize()
+        ea = np.abs(a.cpu().numpy()[pix] - th[:, 0]) / np.maximum(1, np.abs(th[:, 0]))
+        fb = float((K.cpu().numpy() > 1e6).mean())
+        say(f"precision workload, precision={prec}: alpha err max {ea.max():.2e}, fp64 re-solve share {fb:.3%}")
+        assert ea.max() <= (1e-4 if prec == B.GRAM_F64 else 2e-3)
