@@ -303,8 +303,10 @@ int esim_wlr_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int
     a.beta = beta;
     a.resid = resid;
     a.kappa = kappa;
+    int max_r = 0;
+    for (const auto& c : pl->host) max_r = std::max(max_r, static_cast<int>(c.r));
     return hip_check(esim::launch_regress(a, pl->F, pl->f16, pl->host[0].precision, L, pl->blocks_per_cu,
-                                          static_cast<hipStream_t>(stream)),
+                                          max_r, static_cast<hipStream_t>(stream)),
                      "regress");
   } catch (...) {
     return fail(ESIM_E_HIP, "exception");

@@ -71,12 +71,12 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
   const int lane = threadIdx.x & (kWave - 1);
   const int slot = lane / L;
   const int j = lane % L;
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) / kWave;
   const int64_t ngroups = (bd.n + G - 1) / G;
   const int r = C.r, tr = C.tr;
   const int span = 2 * r + 1;
-  for (int64_t g = wave; g < ngroups; g += nwaves) {
+  GroupIter it_groups(ngroups);
+  int64_t g;
+  while (it_groups.next(g)) {
     const int64_t i = g * G + slot;
     int64_t pix = 0;
     int t = 0;
@@ -301,7 +301,7 @@ hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   const int G = kWave / kAdjLanes;
   int64_t blocks = ((a.n + G - 1) / G + kWavesPerBlock - 1) / kWavesPerBlock;
   if (blocks > 1024) blocks = 1024;
-  if (blocks < 1) blocks = 1;
+  blocks = (blocks + 7) / 8 * 8;   // a multiple of the 8 XCDs (see GroupIter)
   hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a.clip, a.items, a.g_alpha, bd);
   hipLaunchKernelGGL(gather_kernel, dim3(grid_for(map_n, 8192)), dim3(256), 0, s, a.clip, bd, a.g_y);
   hipLaunchKernelGGL(rb, dim3(kRedBlocks), dim3(256), 0, s, bd);

@@ -137,7 +137,7 @@ struct RegressArgs {
 // Regression launcher: picks the kernel instance for (F, dtype, precision)
 // and the lanes-per-item L; returns hipSuccess or the launch error.
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
-                          int blocks_per_cu, hipStream_t s);
+                          int blocks_per_cu, int max_r, hipStream_t s);
 int regress_supported_lanes(int F);
 bool regress_supports(int F, int lanes, int precision);
 

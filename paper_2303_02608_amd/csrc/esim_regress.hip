@@ -36,8 +36,8 @@ namespace {
 // FP32 Gram with block-compensated sums (GramC), FP32 Cholesky, and an FP64
 // re-solve of the same compensated Gram for items whose Hager condition
 // estimate exceeds kappa_fp64.
-template <int F, int L, bool F16, bool C32>
-__global__ void __launch_bounds__(256)
+template <int F, int L, bool F16, bool C32, bool ONE = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ONE ? 2 : 1)))
 regress_kernel(RegressArgs a) {
   constexpr int D = F + 2;
   constexpr int P = F + 3;
@@ -47,14 +47,14 @@ regress_kernel(RegressArgs a) {
   const int lane = threadIdx.x & (kWave - 1);
   const int slot = lane / L;
   const int j = lane % L;
-  const int64_t wave = (static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x) / kWave;
-  const int64_t nwaves = (static_cast<int64_t>(gridDim.x) * blockDim.x) / kWave;
   // the device count is clamped to the output length: item i writes index i
   const int64_t n_items =
       a.items ? max(static_cast<int64_t>(0), min(static_cast<int64_t>(a.count[0]), a.n_out)) : 0;
   const int64_t ngroups = a.items ? (n_items + G - 1) / G : a.n_dense_groups;
 
-  for (int64_t g = wave; g < ngroups; g += nwaves) {
+  GroupIter it_groups(ngroups);
+  int64_t g;
+  while (it_groups.next(g)) {
     // ---- which item, clip, pixel and frame this lane group works on.  Items
     //      are bounds-checked (clip, pixel, frame); invalid ones are skipped.
     int my_cl = 0;
@@ -106,18 +106,36 @@ regress_kernel(RegressArgs a) {
       double th[P], rhs[P], Syy, iW, kap = 0.0;
       if constexpr (!C32) {
         Gram<F, double> gm;
-        gm.zero();
-        window_loop<F, L, F16, double>(
-            geo, j, [&](double) { gm.pass_begin(); },
-            [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-              gm.add(w, yd, v, vy);
-            },
-            [&](double vx) { gm.pass_end(vx); });
+        if constexpr (ONE) {
+          // every lane owns one column (2r + 1 <= L, checked by the launcher)
+          gm.zero_onepass();
+          window_loop<F, L, F16, double>(
+              geo, j, [&](double) {},
+              [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+                gm.add_onepass(w, yd, v, vy);
+              },
+              [&](double vx) { gm.fold_onepass(vx); });
+        } else {
+          gm.zero();
+          window_loop<F, L, F16, double>(
+              geo, j, [&](double) { gm.pass_begin(); },
+              [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+                gm.add(w, yd, v, vy);
+              },
+              [&](double vx) { gm.pass_end(vx); });
+        }
         gm.template lane_sum<L>();
         double M[P * (P + 1) / 2], anorm;
         iW = gram_solve<F, double>(gm, C, M, rhs, th, anorm);
         Syy = gm.Syy;
-        if (a.kappa) kap = anorm * hager_inv_norm1<P, double>(M);
+        // the one-pass instances leave the estimate to the general ones (the
+        // launcher never picks them when kappa is requested), which keeps
+        // their register budget within two waves per SIMD
+        if constexpr (!ONE) {
+          if (a.kappa) kap = anorm * hager_inv_norm1<P, double>(M);
+        } else {
+          (void)anorm;
+        }
       } else {
         GramC<F> gc;
         gc.zero();
@@ -191,6 +209,30 @@ KernelFn pick_dtype(bool f16) {
   return f16 ? regress_kernel<F, L, true, false> : regress_kernel<F, L, false, false>;
 }
 
+// One-pass instances (16 lanes per item, window radius <= 7).
+template <int F>
+KernelFn pick_one(bool f16) {
+  return f16 ? regress_kernel<F, 16, true, false, true> : regress_kernel<F, 16, false, false, true>;
+}
+
+KernelFn pick_onepass(int F, bool f16) {
+  switch (F) {
+    case 1: return pick_one<1>(f16);
+    case 2: return pick_one<2>(f16);
+    case 3: return pick_one<3>(f16);
+    case 4: return pick_one<4>(f16);
+    case 5: return pick_one<5>(f16);
+    case 6: return pick_one<6>(f16);
+    case 7: return pick_one<7>(f16);
+    case 8: return pick_one<8>(f16);
+    case 9: return pick_one<9>(f16);
+    case 10: return pick_one<10>(f16);
+    case 11: return pick_one<11>(f16);
+    case 12: return pick_one<12>(f16);
+    default: return nullptr;
+  }
+}
+
 // The compensated-FP32 variant is compiled for the feature counts of the
 // workloads (7 and 10) and for the default lane counts.
 KernelFn pick_c32(int F, int lanes, bool f16) {
@@ -240,13 +282,15 @@ bool regress_supports(int F, int lanes, int precision) {
 }
 
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
-                          int blocks_per_cu, hipStream_t s) {
-  KernelFn fn = precision == ESIM_GRAM_F32C ? pick_c32(F, lanes, f16) : pick(F, lanes, f16);
+                          int blocks_per_cu, int max_r, hipStream_t s) {
+  KernelFn fn = precision == ESIM_GRAM_F32C ? pick_c32(F, lanes, f16)
+                : (lanes == 16 && 2 * max_r + 1 <= 16 && !a.kappa) ? pick_onepass(F, f16)
+                                                       : pick(F, lanes, f16);
   if (!fn) return hipErrorInvalidValue;
   int64_t blocks = (a.max_groups + kWavesPerBlock - 1) / kWavesPerBlock;
   const int64_t cap = static_cast<int64_t>(256) * blocks_per_cu;
   if (blocks > cap) blocks = cap;
-  if (blocks < 1) blocks = 1;
+  blocks = (blocks + 7) / 8 * 8;   // a multiple of the 8 XCDs (see GroupIter)
   hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }

@@ -69,9 +69,15 @@ __device__ __forceinline__ void make_geom(ItemGeom<F, F16, Real>& g, const ClipD
 //   sample(w, yd, v[F], vy, dx, dt, dy, ok) for every sample; ok is false
 //                                       (and w = 0) outside the image, for
 //                                       idle columns and for the weight-0
-//                                       padding row of an odd row count, whose
+//                                       padding rows past the last row, whose
 //                                       (dt, dy) lie past the window
 //   pass_end(vx)                        after each column pass
+//
+// The rows of a column form a three-stage software pipeline: the loads of row
+// k+2 are in flight while the weight of row k+1 is computed and row k is
+// accumulated, so the exponential's latency overlaps independent Gram work.
+// Row offsets advance by uniform (SGPR) amounts; only the validity test and
+// the select are per lane.
 template <int F, int L, bool F16, class Real, class PassBegin, class Sample, class PassEnd>
 __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int j,
                                             PassBegin&& pass_begin, Sample&& sample,
@@ -79,8 +85,13 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
   constexpr uint32_t ES = ItemGeom<F, F16, Real>::ES;
   constexpr Real K = static_cast<Real>(kHalfLog2e);
   const int r = g.r;
-  const int nrows = (g.dt_hi - g.dt_lo + 1) * (2 * r + 1);
-  const int npass = (2 * r + 1 + L - 1) / L;
+  const int span = 2 * r + 1;
+  const int nrows = (g.dt_hi - g.dt_lo + 1) * span;
+  const int npass = (span + L - 1) / L;
+  // per-lane valid row range of the item (rows inside the image)
+  const int dy_lo = -min(r, g.py), dy_hi = min(r, g.H - 1 - g.py);
+  const uint32_t WES = static_cast<uint32_t>(g.W) * ES, W4 = static_cast<uint32_t>(g.W) * 4u;
+  const uint32_t FES = static_cast<uint32_t>(F) * g.HW * ES, HW4 = g.HW * 4u;
   for (int k = 0; k < npass; ++k) {
     const int dx = -r + j + k * L;
     const int col = g.px + dx;
@@ -88,58 +99,74 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
     const Real vx = static_cast<Real>(dx) * g.vx_step;
     const Real kx = K * vx * vx;
     pass_begin(vx);
-    int ldt = g.dt_lo, ldy = -r;   // next row to load
+    // offsets of the window's first row (dt_lo, -r) in this column; rows above
+    // the image wrap as unsigned and are never used (the select takes the
+    // centre instead)
+    const uint32_t vf_base = (static_cast<uint32_t>(g.fc + g.dt_lo) * F * g.HW +
+                              static_cast<uint32_t>((g.py - r) * g.W + col)) * ES;
+    const uint32_t vy_base = (static_cast<uint32_t>(g.fc + g.dt_lo) * g.HW +
+                              static_cast<uint32_t>((g.py - r) * g.W + col)) * 4u;
+    int ldt = 0, ldy = 0;          // next row to load, relative to (dt_lo, -r)
     auto load_row = [&](float& yv, float (&fv)[F]) -> bool {
-      const int row = g.py + ldy;
-      // bitwise tests and selects keep the row addressing branch-free
-      const bool ok = (ldt <= g.dt_hi) & col_ok & (row >= 0) & (row < g.H);
-      const uint32_t pofs = static_cast<uint32_t>(row * g.W + col);
-      const uint32_t fr = static_cast<uint32_t>(g.fc + ldt);
-      const uint32_t vf_row = (fr * F * g.HW + pofs) * ES;
-      const uint32_t vy_row = (fr * g.HW + pofs) * 4u;
-      const uint32_t vf = ok ? vf_row : g.vcen_f;
-      const uint32_t vy = ok ? vy_row : g.vcen_y;
+      const int dy = ldy - r;
+      const bool ok = (ldt <= g.dt_hi - g.dt_lo) & col_ok & (dy >= dy_lo) & (dy <= dy_hi);
+      const uint32_t sof = static_cast<uint32_t>(ldt) * FES + static_cast<uint32_t>(ldy) * WES;
+      const uint32_t soy = static_cast<uint32_t>(ldt) * HW4 + static_cast<uint32_t>(ldy) * W4;
+      const uint32_t vf = ok ? vf_base + sof : g.vcen_f;
+      const uint32_t vy = ok ? vy_base + soy : g.vcen_y;
       yv = ld_f32(g.ry, vy, 0);
 #pragma unroll
       for (int f = 0; f < F; ++f) fv[f] = ld_feat<F16>(g.rf, vf, f * g.HW * ES);
-      if (++ldy > r) {
-        ldy = -r;
+      if (++ldy == span) {
+        ldy = 0;
         ++ldt;
       }
       return ok;
     };
-    int cdt = g.dt_lo, cdy = -r;   // row being used
-    auto use_row = [&](float yv, const float (&fv)[F], bool ok) {
-      const int dy = cdy, dt = cdt;
+    struct Wt {
+      Real w, yd, vy, v[F];
+      int dt, dy;
+      bool ok;
+    };
+    int cdt = g.dt_lo, cdy = -r;   // next row to weigh
+    auto weigh = [&](float yv, const float (&fv)[F], bool ok, Wt& o) {
+      o.dy = cdy;
+      o.dt = cdt;
+      o.ok = ok;
       if (++cdy > r) {
         cdy = -r;
         ++cdt;
       }
-      const Real vy = static_cast<Real>(dy) * g.vy_step;
-      Real v[F];
+      o.vy = static_cast<Real>(o.dy) * g.vy_step;
       Real s0 = 0, s1 = 0;
 #pragma unroll
       for (int f = 0; f < F; ++f) {
-        v[f] = fma(static_cast<Real>(fv[f]), g.sf[2 + f], -g.xcs[f]);
-        if (f & 1) s1 = fma(v[f], v[f], s1);
-        else s0 = fma(v[f], v[f], s0);
+        o.v[f] = fma(static_cast<Real>(fv[f]), g.sf[2 + f], -g.xcs[f]);
+        if (f & 1) s1 = fma(o.v[f], o.v[f], s1);
+        else s0 = fma(o.v[f], o.v[f], s0);
       }
-      const Real arg = fma(s0 + s1, K, fma(K * vy, vy, kx));
+      const Real arg = fma(s0 + s1, K, fma(K * o.vy, o.vy, kx));
       const float e = __builtin_amdgcn_exp2f(static_cast<float>(arg));
-      const Real w = static_cast<Real>(ok ? e : 0.0f);
-      sample(w, static_cast<Real>(yv), v, vy, dx, dt, dy, ok);
+      o.w = static_cast<Real>(ok ? e : 0.0f);
+      o.yd = static_cast<Real>(yv);
     };
-    // two rows per iteration in one basic block (an odd last row is used with
-    // weight 0), so the scheduler can overlap the weight of one row with the
-    // accumulation of the other
+    auto use = [&](const Wt& o) { sample(o.w, o.yd, o.v, o.vy, dx, o.dt, o.dy, o.ok); };
+    // pipeline prologue: rows 0 and 1 loaded, row 0 weighed, row 2 in flight
     float yA, fA[F], yB, fB[F];
-    bool okA = load_row(yA, fA), okB;
+    bool okA = load_row(yA, fA);
+    bool okB = load_row(yB, fB) & (1 < nrows);
+    Wt wA, wB;
+    weigh(yA, fA, okA, wA);
+    okA = load_row(yA, fA) & (2 < nrows);
 #pragma unroll 1
     for (int q = 0; q < nrows; q += 2) {
-      okB = load_row(yB, fB) & (q + 1 < nrows);
-      use_row(yA, fA, okA);
-      okA = load_row(yA, fA);
-      use_row(yB, fB, okB);
+      // wA = row q (weighed), raw B = row q+1, raw A = row q+2
+      weigh(yB, fB, okB, wB);
+      okB = load_row(yB, fB) & (q + 3 < nrows);
+      use(wA);
+      weigh(yA, fA, okA, wA);
+      okA = load_row(yA, fA) & (q + 4 < nrows);
+      use(wB);
     }
     pass_end(vx);
   }
@@ -204,29 +231,79 @@ struct Gram {
       Axf[f] = fma(vx, qF[f], Axf[f]);
     }
   }
+  // One-pass form (every lane owns a single window column): the column sums
+  // are the totals, and the entries with a v_x factor are formed once after
+  // the window loop, so they are not live during it.
+  __device__ __forceinline__ void zero_onepass() {
+    SW = A0y = g0 = Ayy = gy = Syy = 0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) A0f[f] = Ayf[f] = gf[f] = 0;
+#pragma unroll
+    for (int k = 0; k < NA; ++k) Aff[k] = 0;
+  }
+  __device__ __forceinline__ void add_onepass(Real w, Real yd, const Real (&v)[F], Real vy) {
+    const Real wy = w * yd;
+    const Real wvy = w * vy;
+    SW += w;
+    A0y += wvy;
+    g0 += wy;
+    Ayy = fma(wvy, vy, Ayy);
+    gy = fma(wy, vy, gy);
+    Syy = fma(wy, yd, Syy);
+    int qq = 0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      const Real wz = w * v[f];
+      A0f[f] += wz;
+      Ayf[f] = fma(wvy, v[f], Ayf[f]);
+      gf[f] = fma(wz, yd, gf[f]);
+#pragma unroll
+      for (int e = f; e < F; ++e) {
+        Aff[qq] = fma(wz, v[e], Aff[qq]);
+        ++qq;
+      }
+    }
+  }
+  __device__ __forceinline__ void fold_onepass(Real vx) {
+    A0x = vx * SW;
+    Axx = vx * vx * SW;
+    Axy = vx * A0y;
+    gx = vx * g0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) Axf[f] = vx * A0f[f];
+  }
+  // Applies one DPP butterfly step to every total; the steps run in sequence
+  // over all totals (step-major), so consecutive DPP reads never depend on
+  // the previous instruction.
+  template <int CTRL>
+  __device__ __forceinline__ void dpp_step() {
+    auto st = [](Real& v) { v += dpp_d<CTRL>(v); };
+    st(SW);
+    st(A0y);
+    st(g0);
+    st(A0x);
+    st(Axx);
+    st(Axy);
+    st(gx);
+    st(Ayy);
+    st(gy);
+    st(Syy);
+#pragma unroll
+    for (int f = 0; f < F; ++f) {
+      st(A0f[f]);
+      st(Axf[f]);
+      st(Ayf[f]);
+      st(gf[f]);
+    }
+#pragma unroll
+    for (int k = 0; k < NA; ++k) st(Aff[k]);
+  }
   template <int L>
   __device__ __forceinline__ void lane_sum() {
-    if constexpr (L > 1) {
-      SW = group_sum<L>(SW);
-      A0y = group_sum<L>(A0y);
-      g0 = group_sum<L>(g0);
-      A0x = group_sum<L>(A0x);
-      Axx = group_sum<L>(Axx);
-      Axy = group_sum<L>(Axy);
-      gx = group_sum<L>(gx);
-      Ayy = group_sum<L>(Ayy);
-      gy = group_sum<L>(gy);
-      Syy = group_sum<L>(Syy);
-#pragma unroll
-      for (int f = 0; f < F; ++f) {
-        A0f[f] = group_sum<L>(A0f[f]);
-        Axf[f] = group_sum<L>(Axf[f]);
-        Ayf[f] = group_sum<L>(Ayf[f]);
-        gf[f] = group_sum<L>(gf[f]);
-      }
-#pragma unroll
-      for (int k = 0; k < NA; ++k) Aff[k] = group_sum<L>(Aff[k]);
-    }
+    if constexpr (L >= 2) dpp_step<0xB1>();
+    if constexpr (L >= 4) dpp_step<0x4E>();
+    if constexpr (L >= 8) dpp_step<0x141>();
+    if constexpr (L >= 16) dpp_step<0x140>();
   }
 };
 
@@ -342,7 +419,38 @@ struct GramC {
 
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// Solves L L^T x = b with the packed factor.
+// Wave-group iteration with XCD affinity.  Workgroups are dispatched to the 8
+// XCDs round-robin by block index, so block b runs on XCD b % 8.  When the grid
+// is a multiple of 8 blocks, XCD x walks the contiguous x-th eighth of the
+// groups, which keeps spatially adjacent items (sharing window rows) in the
+// same L2; otherwise a plain grid stride is used.
+struct GroupIter {
+  int64_t g, end, step;
+  __device__ __forceinline__ GroupIter(int64_t ngroups) {
+    const int64_t nblk = gridDim.x;
+    const int64_t wib = threadIdx.x / kWave;            // wave in block
+    const int64_t wpb = blockDim.x / kWave;
+    if (nblk >= 8 && nblk % 8 == 0) {
+      const int64_t x = blockIdx.x % 8;
+      const int64_t chunk = (ngroups + 7) / 8;
+      g = x * chunk + (blockIdx.x / 8) * wpb + wib;
+      end = min(ngroups, (x + 1) * chunk);
+      step = (nblk / 8) * wpb;
+    } else {
+      g = static_cast<int64_t>(blockIdx.x) * wpb + wib;
+      end = ngroups;
+      step = nblk * wpb;
+    }
+  }
+  __device__ __forceinline__ bool next(int64_t& out) {
+    if (g >= end) return false;
+    out = g;
+    g += step;
+    return true;
+  }
+};
+
+// Solves L L^T x = b with the packed factor (its diagonal holds 1 / L_ii).
 template <int P, class Real>
 __device__ __forceinline__ void chol_solve(const Real (&M)[P * (P + 1) / 2], const Real (&b)[P],
                                            Real (&x)[P]) {
@@ -351,18 +459,19 @@ __device__ __forceinline__ void chol_solve(const Real (&M)[P * (P + 1) / 2], con
     Real v = b[i];
 #pragma unroll
     for (int k = 0; k < i; ++k) v -= M[tri(i, k)] * x[k];
-    x[i] = v / M[tri(i, i)];
+    x[i] = v * M[tri(i, i)];
   }
 #pragma unroll
   for (int i = P - 1; i >= 0; --i) {
     Real v = x[i];
 #pragma unroll
     for (int k = i + 1; k < P; ++k) v -= M[tri(k, i)] * x[k];
-    x[i] = v / M[tri(i, i)];
+    x[i] = v * M[tri(i, i)];
   }
 }
 
-// In-place packed Cholesky; a non-positive pivot yields NaN.
+// In-place packed Cholesky A = L L^T; the diagonal slots receive 1 / L_ii (the
+// solves multiply by it).  A non-positive pivot yields NaN.
 template <int P, class Real>
 __device__ __forceinline__ void cholesky_inplace(Real (&M)[P * (P + 1) / 2]) {
 #pragma unroll
@@ -372,7 +481,7 @@ __device__ __forceinline__ void cholesky_inplace(Real (&M)[P * (P + 1) / 2]) {
     for (int k = 0; k < c; ++k) s -= M[tri(c, k)] * M[tri(c, k)];
     const Real d = s > Real(0) ? sqrt(s) : static_cast<Real>(__builtin_nan(""));
     const Real id = Real(1) / d;
-    M[tri(c, c)] = d;
+    M[tri(c, c)] = id;
 #pragma unroll
     for (int i = c + 1; i < P; ++i) {
       Real v = M[tri(i, c)];

@@ -119,6 +119,27 @@ def test_lanes_per_item_variants(small_clip, lanes):
     _check(*out, ref, f"lanes={lanes}", unit_bandwidth=False)
 
 
+@pytest.mark.parametrize("r", [3, 7])
+def test_one_pass_instance(small_clip, r):
+    """16 lanes per item with 2r + 1 <= 16 and no condition output selects the
+    one-pass kernel instance (each lane owns one column)."""
+    cfg = small_clip["cfg"]
+    p = B.Params(r=r, tr=1, C=cfg["C"], h=1.1, b=[0.9, 1.2, 1.0, 1.1, 0.8, 1.0, 1.3, 0.9, 1.0])
+    say(f"one-pass instance r={r}")
+    y, fd = to_dev(small_clip["E"], small_clip["feat"])
+    plan = B.Plan([y], [fd], [p])
+    plan.set_schedule(16, 16, 2)
+    HW = plan.npix
+    a = torch.empty(HW, device="cuda")
+    b = torch.empty((plan.D, HW), device="cuda")
+    R = torch.empty(HW, device="cuda")
+    B.regress(plan, 9, None, None, HW, a, b, R)
+    torch.cuda.synchronize()
+    ref = _oracle_all(small_clip["E"], small_clip["feat"], p, 9, kappa=False)
+    _check(a.cpu().numpy(), b.cpu().numpy(), R.cpu().numpy(), None, ref, f"one-pass r={r}",
+           unit_bandwidth=False)
+
+
 def test_f16_features(small_clip):
     cfg = small_clip["cfg"]
     feat = small_clip["feat"].astype(np.float16)
