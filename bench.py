@@ -58,7 +58,7 @@ def regress_flops(omega, F):
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("esim_regress.hip", "esim_internal.h"):
+    for f in ("esim_regress_impl.h", "esim_wlr.h", "esim_internal.h"):
         with open(os.path.join(ROOT, "paper_2303_02608_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
@@ -210,6 +210,10 @@ def main():
     # The thresholded path launches the regression kernel twice over: one dense
     # launch at frame 0 (lanes_dense instance) and one work-list launch per
     # later frame (lanes_list instance).  The dominant kernel is the list one.
+    # The pass runs the frames as separate threshold / regress / events calls so
+    # that HIP events can bracket each regression launch on its stream: the
+    # same kernel instance, grid and items as inside esim_step (which only
+    # differs in writing the model to the state instead of output arrays).
     stream = torch.cuda.current_stream()
     marks = []
     orig = B.regress
@@ -224,7 +228,7 @@ def main():
     B.regress = timed_regress
     try:
         B.log_brightness(E, out=y)
-        sim.enqueue("thresholded")
+        sim.enqueue("thresholded", fused=False)
         torch.cuda.synchronize()
     finally:
         B.regress = orig
@@ -255,7 +259,7 @@ def main():
         marks.clear()
         B.regress = timed_regress
         try:
-            sim.enqueue("exhaustive")
+            sim.enqueue("exhaustive", fused=False)
             torch.cuda.synchronize()
         finally:
             B.regress = orig

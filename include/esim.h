@@ -137,7 +137,7 @@ int esim_plan_destroy(esim_plan plan);
 /* Total pixels over the plan's clips (sum of H*W): the length of dl, of dense
  * regression outputs and of a work list, without padding. */
 int64_t esim_plan_pixels(esim_plan plan);
-/* Work-list capacity a threshold call may need: pixels plus per-clip padding. */
+/* Work-list capacity a threshold call may need: the plan's pixels. */
 int64_t esim_plan_worklist_capacity(esim_plan plan);
 /* First pixel of clip c in the concatenated pixel range. */
 int64_t esim_plan_pixel_offset(esim_plan plan, int32_t c);
@@ -161,9 +161,8 @@ int esim_log_brightness(const float* E, float* y, int64_t n, float eps, void* st
  * channels (computed in FP64 from the FP32 state), written to dl[pixel offset
  * + p] (NaN for clips inactive at t); a pixel is flagged when dL^2 >= C^2.
  * Flagged pixels are compacted into worklist as items (clip << 32 | p), in
- * ascending (clip, p) order; each clip's segment is padded with -1 entries to
- * a multiple of the plan's group size when the plan has more than one clip.
- * count[0] = work-list length including padding, count[1] = flagged pixels.
+ * ascending (clip, p) order.  count[0] = count[1] = flagged pixels (the work-list
+ * length; a wave of the regression may straddle two clips).
  * dl must hold esim_plan_pixels values, worklist
  * esim_plan_worklist_capacity items, count two int32. */
 int esim_wlr_threshold(esim_plan plan, int32_t t, float* dl, int64_t* worklist,
@@ -215,6 +214,26 @@ int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const i
 int esim_events(esim_plan plan, int32_t t, int32_t mode, const int64_t* worklist,
                 const int32_t* count, float* dl, const float* alpha, const float* beta,
                 int64_t n_out, esim_events_buf* ev, void* stream);
+
+/* One frame of a conversion (Sec. 2.2; Sec. 3) with the plan's own work
+ * buffers, in as few launches as the step allows; the same results as the
+ * per-frame calls above (same kernels and arithmetic):
+ *   ESIM_INIT:        regress every pixel active at t and store the models in
+ *                     the state (no events).
+ *   ESIM_THRESHOLDED: threshold (Prop. 1) at t >= 1, append the flagged
+ *                     pixels' events (sign of dL, during the compaction), and
+ *                     regress the flagged pixels, each regression writing its
+ *                     model straight into the state.
+ *   ESIM_EXHAUSTIVE:  regress every pixel, then eq. (1) on alpha (as
+ *                     esim_events).
+ *   ESIM_RAW:         eq. (1) on y_t.
+ * dl (nullable, esim_plan_pixels values) receives the compared change.
+ * The plan's internal work list and dense outputs are overwritten; calls on
+ * one plan must be ordered on one stream.  Events are appended at *ev->count
+ * (the true total is always counted; entries beyond capacity are dropped).
+ * Errors: E_INVAL (t, mode, missing state or events buffer), E_UNSUPPORTED. */
+int esim_step(esim_plan plan, int32_t t, int32_t mode, float* dl, esim_events_buf* ev,
+              void* stream);
 
 /* Adjoint of alpha (eqs. 4-5 differentiated) at n regressions.  items
  * carry their frame (bits [44,63)) and must be distinct; g_alpha[n] is the

@@ -69,6 +69,7 @@ SIGNATURES = {
     "esim_wlr_threshold": (_i32, [_vp, _i32, _vp, _vp, _vp, _vp]),
     "esim_wlr_regress": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp]),
     "esim_events": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp, _i64, _vp, _vp]),
+    "esim_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "esim_backward_scratch_bytes": (_sz, [_vp, _i64]),
     "esim_wlr_backward": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
     "esim_status_string": (ctypes.c_char_p, [_i32]),
@@ -255,6 +256,13 @@ def events(plan: Plan, t: int, mode: int, ev: Optional[Events], worklist=None, c
     _check(load().esim_events(plan.h, t, mode, _ptr(worklist), _ptr(count), _ptr(dl), _ptr(alpha),
                               _ptr(beta), n_out, ctypes.byref(evs) if evs is not None else None,
                               _stream(stream)), "events")
+
+
+def step(plan: Plan, t: int, mode: int, ev: Optional[Events] = None, dl=None, stream=None):
+    """One frame of a conversion with the plan's own work buffers (esim_step)."""
+    evs = ev.struct() if ev is not None else None
+    _check(load().esim_step(plan.h, t, mode, _ptr(dl), ctypes.byref(evs) if evs is not None else None,
+                            _stream(stream)), "step")
 
 
 def backward_scratch_bytes(plan: Plan, n: int) -> int:

@@ -17,6 +17,9 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libesim.so")
 SOURCES = ["esim_api.hip", "esim_compact.hip", "esim_regress.hip", "esim_backward.hip"]
+# the regression kernels of feature count f are compiled from esim_regress_inst.hip
+# with -DESIM_REGRESS_F=f, one object each, so that they build in parallel
+REGRESS_F = range(1, 13)
 ARCH = os.environ.get("ESIM_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -25,9 +28,10 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-I", INCLUDE, "-I", CSRC, "-Wall", "-Wno-unused-function"]
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC] + FLAGS + ["-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(job) -> str:
+    src, defs, tag = job
+    obj = os.path.join(BUILD, src.replace(".hip", tag + ".o"))
+    cmd = [HIPCC] + FLAGS + defs + ["-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stdout}\n{r.stderr}")
@@ -37,7 +41,9 @@ def _compile(src: str) -> str:
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
+        jobs = [("esim_regress_inst.hip", [f"-DESIM_REGRESS_F={f}"], f"_f{f}") for f in
+                reversed(REGRESS_F)] + [(s, [], "") for s in SOURCES]
+        objs = list(ex.map(_compile, jobs))
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)

@@ -23,11 +23,15 @@ struct esim_plan_s {
   int64_t nblk = 0;
   int64_t wl_capacity = 0;
   int64_t dense_groups[5] = {0, 0, 0, 0, 0};
-  int pad = 1;             // work-list padding per clip segment
   int lanes_dense = 4;     // lanes per regression item, dense launches
   int lanes_list = 16;     // lanes per regression item, work-list launches
   int blocks_per_cu = 4;   // persistent grid: 256 CUs x this many blocks
   uint64_t max_feat_bytes = 0;
+  // work buffers of esim_step (allocated with the plan)
+  void* step_mem = nullptr;
+  int64_t* step_wl = nullptr;     // [wl_capacity]
+  int32_t* step_count = nullptr;  // [2]
+  float* step_alpha = nullptr;    // [npix]
 };
 
 namespace {
@@ -49,7 +53,44 @@ int hip_check(hipError_t e, const char* where) {
   return ok();
 }
 
-constexpr int kMultiClipPad = 32;  // multiple of every wave-group size used
+
+}  // namespace
+
+namespace {
+
+int launch_plan_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int32_t* count,
+                        int64_t n_out, float* alpha, float* beta, float* resid, float* kappa,
+                        bool update_state, hipStream_t stream) {
+  const int L = worklist ? pl->lanes_list : pl->lanes_dense;
+  if (!esim::regress_supports(pl->F, L, pl->host[0].precision))
+    return fail(ESIM_E_UNSUPPORTED, "no kernel instance for this F, lane count and precision");
+  esim::RegressArgs a{};
+  a.clips = pl->dev;
+  a.nclips = pl->nclips;
+  a.t = t;
+  a.items = worklist;
+  a.count = count;
+  a.n_dense_groups = pl->dense_groups[esim::lanes_index(L)];
+  const int G = esim::kWave / L;
+  a.max_groups = worklist ? (std::max<int64_t>(n_out, 1) + G - 1) / G : a.n_dense_groups;
+  a.n_out = n_out;
+  a.alpha = alpha;
+  a.beta = beta;
+  a.resid = resid;
+  a.kappa = kappa;
+  a.update_state = update_state ? 1 : 0;
+  int max_r = 0;
+  for (const auto& c : pl->host) max_r = std::max(max_r, static_cast<int>(c.r));
+  return hip_check(esim::launch_regress(a, pl->F, pl->f16, pl->host[0].precision, L, pl->blocks_per_cu,
+                                        max_r, stream),
+                   "regress");
+}
+
+bool full_state(esim_plan pl) {
+  for (const auto& c : pl->host)
+    if (!c.st_beta || !c.st_xref || !c.st_alpha || !c.st_tref) return false;
+  return true;
+}
 
 }  // namespace
 
@@ -84,7 +125,6 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     pl->nclips = nclips;
     pl->F = clips[0].F;
     pl->f16 = clips[0].feat_dtype == ESIM_F16;
-    pl->pad = nclips > 1 ? kMultiClipPad : 1;
     int64_t pix = 0, blk = 0, grp[5] = {0, 0, 0, 0, 0};
     int64_t wl = 0;
     for (int c = 0; c < nclips; ++c) {
@@ -167,7 +207,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       }
       pix += cd.HW;
       blk += cd.nblk;
-      wl += cd.HW + (pl->pad - 1);
+      wl += cd.HW;
       const uint64_t fb = static_cast<uint64_t>(k.T) * k.F * cd.HW * (cd.feat_f16 ? 2u : 4u);
       const uint64_t wb = static_cast<uint64_t>(2 * p.tr + 1) * k.F * cd.HW * (cd.feat_f16 ? 2u : 4u);
       if (wb >= (1ull << 32) || static_cast<uint64_t>(2 * p.tr + 1) * cd.HW * 4u >= (1ull << 32)) {
@@ -196,10 +236,6 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     off = align(off + sizeof(uint64_t) * blk * esim::kWavesPerBlock);
     const size_t o_pol = off;
     off = align(off + sizeof(uint64_t) * blk * esim::kWavesPerBlock);
-    const size_t o_seg = off;
-    off = align(off + sizeof(int64_t) * nclips);
-    const size_t o_pre = off;
-    off = align(off + sizeof(int64_t) * nclips);
     const size_t o_misc = off;
     off = align(off + sizeof(int64_t) * 4);
     hipError_t e = hipMalloc(&pl->ws_mem, off);
@@ -213,8 +249,6 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     pl->ws.boffset = reinterpret_cast<int64_t*>(m + o_boff);
     pl->ws.flags = reinterpret_cast<uint64_t*>(m + o_flags);
     pl->ws.pol = reinterpret_cast<uint64_t*>(m + o_pol);
-    pl->ws.seg_start = reinterpret_cast<int64_t*>(m + o_seg);
-    pl->ws.seg_prefix = reinterpret_cast<int64_t*>(m + o_pre);
     pl->ws.misc = reinterpret_cast<int64_t*>(m + o_misc);
     e = hipMemcpy(pl->dev, pl->host.data(), clip_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(m + o_bcount, 0, off - o_bcount);
@@ -223,6 +257,26 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       hipFree(pl->ws_mem);
       delete pl;
       return hip_check(e, "plan upload");
+    }
+    // esim_step buffers: work list, count, dense alpha
+    {
+      size_t so = 0;
+      const size_t s_wl = so;
+      so = align(so + sizeof(int64_t) * std::max<int64_t>(wl, 1));
+      const size_t s_cnt = so;
+      so = align(so + sizeof(int32_t) * 2);
+      const size_t s_al = so;
+      so = align(so + sizeof(float) * pix);
+      e = hipMalloc(&pl->step_mem, so);
+      if (e != hipSuccess) {
+        hipFree(pl->ws_mem);
+        delete pl;
+        return hip_check(e, "hipMalloc(step buffers)");
+      }
+      char* sm = static_cast<char*>(pl->step_mem);
+      pl->step_wl = reinterpret_cast<int64_t*>(sm + s_wl);
+      pl->step_count = reinterpret_cast<int32_t*>(sm + s_cnt);
+      pl->step_alpha = reinterpret_cast<float*>(sm + s_al);
     }
     *out = pl;
     return ok();
@@ -236,6 +290,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
 int esim_plan_destroy(esim_plan pl) {
   if (!pl) return ok();
   if (pl->ws_mem) hipFree(pl->ws_mem);
+  if (pl->step_mem) hipFree(pl->step_mem);
   delete pl;
   return ok();
 }
@@ -267,7 +322,7 @@ int esim_wlr_threshold(esim_plan pl, int32_t t, float* dl, int64_t* worklist, in
       if (!c.st_beta || !c.st_xref || !c.st_alpha || !c.st_tref)
         return fail(ESIM_E_INVAL, "threshold needs the full state (alpha, beta, xref, tref)");
     return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold,
-                                               dl, nullptr, pl->ws, pl->pad, worklist, count, nullptr,
+                                               dl, nullptr, pl->ws, worklist, count, nullptr,
                                                static_cast<hipStream_t>(stream)),
                      "threshold");
   } catch (...) {
@@ -286,28 +341,8 @@ int esim_wlr_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int
     if (n_out < 0) return fail(ESIM_E_INVAL, "n_out < 0");
     if (t < 0 && pl->max_feat_bytes >= (1ull << 32))
       return fail(ESIM_E_UNSUPPORTED, "per-item frames need feature arrays below 4 GiB");
-    const int L = worklist ? pl->lanes_list : pl->lanes_dense;
-    if (!esim::regress_supports(pl->F, L, pl->host[0].precision))
-      return fail(ESIM_E_UNSUPPORTED, "no kernel instance for this F, lane count and precision");
-    esim::RegressArgs a{};
-    a.clips = pl->dev;
-    a.nclips = pl->nclips;
-    a.t = t;
-    a.items = worklist;
-    a.count = count;
-    a.n_dense_groups = pl->dense_groups[esim::lanes_index(L)];
-    const int G = esim::kWave / L;
-    a.max_groups = worklist ? (std::max<int64_t>(n_out, 1) + G - 1) / G : a.n_dense_groups;
-    a.n_out = n_out;
-    a.alpha = alpha;
-    a.beta = beta;
-    a.resid = resid;
-    a.kappa = kappa;
-    int max_r = 0;
-    for (const auto& c : pl->host) max_r = std::max(max_r, static_cast<int>(c.r));
-    return hip_check(esim::launch_regress(a, pl->F, pl->f16, pl->host[0].precision, L, pl->blocks_per_cu,
-                                          max_r, static_cast<hipStream_t>(stream)),
-                     "regress");
+    return launch_plan_regress(pl, t, worklist, count, n_out, alpha, beta, resid, kappa, false,
+                               static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(ESIM_E_HIP, "exception");
   }
@@ -345,9 +380,53 @@ int esim_events(esim_plan pl, int32_t t, int32_t mode, const int64_t* worklist, 
       return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t,
                                                  mode == ESIM_EXHAUSTIVE ? esim::kFlagExhaustive
                                                                          : esim::kFlagRaw,
-                                                 dl, alpha, pl->ws, 1, nullptr, nullptr, &ed, s),
+                                                 dl, alpha, pl->ws, nullptr, nullptr, &ed, s),
                        "events");
     }
+    return fail(ESIM_E_INVAL, "bad mode");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+int esim_step(esim_plan pl, int32_t t, int32_t mode, float* dl, esim_events_buf* ev, void* stream) {
+  try {
+    if (!pl) return fail(ESIM_E_INVAL, "null plan");
+    if (t < 0) return fail(ESIM_E_INVAL, "t < 0");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (mode == ESIM_INIT || mode == ESIM_THRESHOLDED) {
+      if (!full_state(pl)) return fail(ESIM_E_INVAL, "the step needs the full state (alpha, beta, xref, tref)");
+    } else {
+      for (const auto& c : pl->host)
+        if (!c.st_alpha) return fail(ESIM_E_INVAL, "state alpha is null");
+    }
+    if (mode == ESIM_INIT)
+      return launch_plan_regress(pl, t, nullptr, nullptr, pl->npix, nullptr, nullptr, nullptr, nullptr,
+                                 true, s);
+    if (!ev || !ev->x || !ev->y || !ev->t || !ev->p || !ev->count || ev->capacity < 0)
+      return fail(ESIM_E_INVAL, "events buffer incomplete");
+    esim::EventsDev ed{ev->x, ev->y, ev->t, ev->p, ev->clip, ev->capacity, ev->count};
+    if (mode == ESIM_THRESHOLDED) {
+      int rc = hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold,
+                                                   dl, nullptr, pl->ws, pl->step_wl,
+                                                   pl->step_count, &ed, s),
+                         "step(threshold)");
+      if (rc != ESIM_OK) return rc;
+      return launch_plan_regress(pl, t, pl->step_wl, pl->step_count, pl->wl_capacity, nullptr, nullptr,
+                                 nullptr, nullptr, true, s);
+    }
+    if (mode == ESIM_EXHAUSTIVE) {
+      int rc = launch_plan_regress(pl, t, nullptr, nullptr, pl->npix, pl->step_alpha, nullptr, nullptr,
+                                   nullptr, false, s);
+      if (rc != ESIM_OK) return rc;
+      return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagExhaustive, dl,
+                                                 pl->step_alpha, pl->ws, nullptr, nullptr, &ed, s),
+                       "step(exhaustive)");
+    }
+    if (mode == ESIM_RAW)
+      return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagRaw, dl,
+                                                 nullptr, pl->ws, nullptr, nullptr, &ed, s),
+                       "step(raw)");
     return fail(ESIM_E_INVAL, "bad mode");
   } catch (...) {
     return fail(ESIM_E_HIP, "exception");

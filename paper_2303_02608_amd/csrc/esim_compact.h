@@ -20,12 +20,17 @@ struct EventsDev {
 
 hipError_t launch_log(const float* E, float* y, int64_t n, float eps, hipStream_t s);
 
-// flag -> scan -> scatter.  mode kFlagThreshold writes the work list and
-// count; the other modes append events to ev.
+// Grids of at most this many blocks skip the scan kernel: each scatter block
+// sums the counts before it (at most 16 KiB of reads).
+constexpr int64_t kDirectPrefixBlocks = 4096;
+
+// flag -> (scan) -> scatter.  mode kFlagThreshold writes the work list and
+// count (count[0] = count[1] = flagged pixels), and with ev also appends the
+// flagged pixels' events (the sign of the threshold's change); the other
+// modes append events to ev.
 hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
-                               float* dl, const float* alpha, const Workspace& ws, int pad,
-                               int64_t* worklist, int32_t* count, const EventsDev* ev,
-                               hipStream_t s);
+                               float* dl, const float* alpha, const Workspace& ws, int64_t* worklist,
+                               int32_t* count, const EventsDev* ev, hipStream_t s);
 
 hipError_t launch_list_events(const ClipDev* clips, int nclips, int t, const int64_t* worklist,
                               const int32_t* count, int64_t max_items, const float* dl,

@@ -8,14 +8,19 @@
 //                                     pixel); flag when dL^2 >= C^2;
 //                        exhaustive - eq. 1 on the regressed alpha against L_ref;
 //                        raw        - eq. 1 on y against L_ref;
-//                      wave ballots of the flags and polarities, block counts.
-//   scan_kernel        one block: exclusive scan of the block counts per clip
-//                      (segments padded for multi-clip work lists), event base.
-//   scatter_kernel     rank = block offset + popcounts of the ballots below the
-//                      lane; writes the work list (threshold) or the events.
+//                      wave ballots of the flags and polarities, block counts;
+//                      block 0 records the event base.
+//   scan_kernel        one block: exclusive scan of the block counts (only for
+//                      grids above kDirectPrefixBlocks blocks).
+//   scatter_kernel     each block's offset: the scan's, or the sum of the
+//                      counts of the blocks before it (read directly, no
+//                      inter-block signalling); rank = offset + popcounts of
+//                      the ballots below the lane; writes the work list
+//                      (threshold) and/or the events; the last block writes
+//                      the count and advances the event count.
 //   list_events_kernel events of the work-list items and the state update
 //                      (Sec. 2.2: the model at the last event is kept until the
-//                      pixel's next event); its last block advances the
+//                      pixel's next event); advance_kernel then advances the
 //                      event count.
 //   init_kernel        state <- the models of frame t (no events).
 #include "esim_internal.h"
@@ -23,15 +28,6 @@
 
 namespace esim {
 namespace {
-
-__device__ __forceinline__ float feat_at(const ClipDev& C, int t, int f, int64_t p) {
-  const int64_t i = (static_cast<int64_t>(t) * C.F + f) * C.HW + p;
-  if (C.feat_f16) {
-    const uint16_t h = static_cast<const uint16_t*>(C.feat)[i];
-    return static_cast<float>(__builtin_bit_cast(_Float16, h));
-  }
-  return static_cast<const float*>(C.feat)[i];
-}
 
 __device__ __forceinline__ int block_clip(const ClipDev* clips, int nclips, int64_t b) {
   int cl = 0;
@@ -47,9 +43,40 @@ __global__ void __launch_bounds__(256) log_kernel(const float* __restrict__ E, f
     y[i] = logf(E[i] + eps);
 }
 
+// Exclusive scan of one value per thread of the block (blockDim.x a multiple
+// of the wave size, at most 1024); returns this thread's exclusive prefix and
+// the block total in *total.
+__device__ int64_t block_scan(int64_t v, int64_t* sh, int64_t* total) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int nw = blockDim.x / kWave;
+  int64_t x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int64_t y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) sh[w] = x;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int64_t run = 0;
+    for (int k = 0; k < nw; ++k) {
+      const int64_t s = sh[k];
+      sh[k] = run;
+      run += s;
+    }
+    sh[16] = run;
+  }
+  __syncthreads();
+  const int64_t ex = sh[w] + x - v;
+  *total = sh[16];
+  __syncthreads();
+  return ex;
+}
+
 __global__ void __launch_bounds__(kBlock)
 flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, float* __restrict__ dl,
-            const float* __restrict__ alpha, Workspace ws) {
+            const float* __restrict__ alpha, Workspace ws, const int64_t* __restrict__ ev_count) {
   __shared__ int wcount[kWavesPerBlock];
   const int64_t b = blockIdx.x;
   const int cl = block_clip(clips, nclips, b);
@@ -65,7 +92,7 @@ flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, floa
         for (int f = 0; f < C.F; ++f) {
           const double bf = C.st_beta[f * C.HW + p];
           const double xf = C.st_xref[f * C.HW + p];
-          d = fma(bf, static_cast<double>(feat_at(C, t, f, p)) - xf, d);
+          d = fma(bf, static_cast<double>(feat_value(C, t, f, p)) - xf, d);
         }
         flag = d * d >= C.C * C.C;
         pos = d > 0.0;
@@ -101,86 +128,57 @@ flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, floa
     int s = 0;
     for (int k = 0; k < kWavesPerBlock; ++k) s += wcount[k];
     ws.bcount[b] = s;
+    // the event base of this step (the count is advanced by the scatter)
+    if (b == 0) ws.misc[0] = ev_count ? *ev_count : 0;
   }
 }
 
-// Exclusive scan of 1024 values held one per thread; returns the exclusive
-// prefix of this thread and writes the total to *total.
-__device__ int64_t block_scan_1024(int64_t v, int64_t* sh, int64_t* total) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  int64_t x = v;
+// One block: exclusive scan of the block counts into ws.boffset.
+__global__ void __launch_bounds__(1024) scan_kernel(Workspace ws, int64_t nblk) {
+  __shared__ int64_t sh[17];
+  const int64_t nt = blockDim.x;
+  const int64_t chunk = (nblk + nt - 1) / nt;
+  const int64_t lo = min(nblk, chunk * threadIdx.x);
+  const int64_t hi = min(nblk, chunk * (threadIdx.x + 1));
+  int64_t s = 0;
+  for (int64_t b = lo; b < hi; ++b) s += ws.bcount[b];
+  int64_t tot;
+  int64_t off = block_scan(s, sh, &tot);
+  for (int64_t b = lo; b < hi; ++b) {
+    ws.boffset[b] = off;
+    off += ws.bcount[b];
+  }
+}
+
+// Sum of the counts of blocks [0, b), by one block.
+__device__ int64_t counts_before(const Workspace& ws, int64_t b) {
+  __shared__ int64_t red[kWavesPerBlock];
+  int64_t s = 0;
+  for (int64_t k = threadIdx.x; k < b; k += blockDim.x) s += ws.bcount[k];
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int64_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == kWave - 1) sh[w] = x;
+  for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
   __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int k = 0; k < 1024 / kWave; ++k) {
-      const int64_t s = sh[k];
-      sh[k] = run;
-      run += s;
-    }
-    sh[1024 / kWave] = run;
-  }
-  __syncthreads();
-  const int64_t ex = sh[w] + x - v;
-  *total = sh[1024 / kWave];
-  __syncthreads();
-  return ex;
-}
-
-__global__ void __launch_bounds__(1024)
-scan_kernel(const ClipDev* __restrict__ clips, int nclips, Workspace ws, int pad, int64_t* worklist,
-            int32_t* count, int64_t* ev_count) {
-  __shared__ int64_t sh[1024 / kWave + 1];
-  __shared__ int64_t base_sh;
-  if (threadIdx.x == 0) base_sh = ev_count ? *ev_count : 0;
-  __syncthreads();
-  const int64_t base = base_sh;
-  int64_t run = 0, real = 0;
-  for (int c = 0; c < nclips; ++c) {
-    const int64_t nb = clips[c].nblk, b0 = clips[c].blk_off;
-    if (threadIdx.x == 0) {
-      ws.seg_start[c] = run;
-      ws.seg_prefix[c] = real;
-    }
-    const int64_t chunk = (nb + 1023) / 1024;
-    const int64_t lo = b0 + min(nb, chunk * threadIdx.x);
-    const int64_t hi = b0 + min(nb, chunk * (threadIdx.x + 1));
-    int64_t s = 0;
-    for (int64_t b = lo; b < hi; ++b) s += ws.bcount[b];
-    int64_t tot;
-    int64_t off = block_scan_1024(s, sh, &tot) + run + base;
-    for (int64_t b = lo; b < hi; ++b) {
-      ws.boffset[b] = off;
-      off += ws.bcount[b];
-    }
-    run += tot;
-    real += tot;
-    if (pad > 1 && worklist) {
-      const int64_t npad = (pad - run % pad) % pad;
-      for (int64_t k = threadIdx.x; k < npad; k += blockDim.x) worklist[run + k] = -1;
-      run += npad;
-    }
-  }
-  if (threadIdx.x == 0) {
-    if (count) {
-      count[0] = static_cast<int32_t>(run);
-      count[1] = static_cast<int32_t>(real);
-    }
-    if (ev_count) *ev_count = base + real;
-    ws.misc[0] = base;
-  }
+  int64_t tot = 0;
+#pragma unroll
+  for (int k = 0; k < kWavesPerBlock; ++k) tot += red[k];
+  return tot;
 }
 
 __global__ void __launch_bounds__(kBlock)
-scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, Workspace ws,
-               int64_t* __restrict__ worklist, EventsDev ev) {
+scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, Workspace ws, int direct,
+               int64_t* __restrict__ worklist, int32_t* __restrict__ count, EventsDev ev) {
   const int64_t b = blockIdx.x;
+  const int64_t off0 = direct ? counts_before(ws, b) : ws.boffset[b];
+  const int64_t base = ws.misc[0];
+  if (b == gridDim.x - 1 && threadIdx.x == 0) {
+    const int64_t total = off0 + ws.bcount[b];
+    if (count) {
+      count[0] = static_cast<int32_t>(total);
+      count[1] = static_cast<int32_t>(total);
+    }
+    if (ev.count) *ev.count = base + total;
+  }
   const int cl = block_clip(clips, nclips, b);
   const ClipDev& C = clips[cl];
   const int lane = threadIdx.x & (kWave - 1);
@@ -188,18 +186,20 @@ scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, W
   const uint64_t m = ws.flags[b * kWavesPerBlock + w];
   if (!((m >> lane) & 1ull)) return;
   const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
-  int64_t off = ws.boffset[b];
+  int64_t off = off0;
   for (int k = 0; k < w; ++k) off += __popcll(ws.flags[b * kWavesPerBlock + k]);
   off += __popcll(m & ((1ull << lane) - 1ull));
-  if (mode == kFlagThreshold) {
-    worklist[off] = (static_cast<int64_t>(cl) << 32) | p;
-  } else if (off < ev.capacity) {
-    const bool pos = (ws.pol[b * kWavesPerBlock + w] >> lane) & 1ull;
-    ev.x[off] = static_cast<int32_t>(p % C.W);
-    ev.y[off] = static_cast<int32_t>(p / C.W);
-    ev.t[off] = t;
-    ev.p[off] = pos ? 1 : -1;
-    if (ev.clip) ev.clip[off] = cl;
+  if (mode == kFlagThreshold && worklist) worklist[off] = (static_cast<int64_t>(cl) << 32) | p;
+  if (ev.x) {
+    const int64_t e = base + off;
+    if (e < ev.capacity) {
+      const bool pos = (ws.pol[b * kWavesPerBlock + w] >> lane) & 1ull;
+      ev.x[e] = static_cast<int32_t>(p % C.W);
+      ev.y[e] = static_cast<int32_t>(p / C.W);
+      ev.t[e] = t;
+      ev.p[e] = pos ? 1 : -1;
+      if (ev.clip) ev.clip[e] = cl;
+    }
   }
 }
 
@@ -220,21 +220,11 @@ list_events_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const i
   const int64_t base = *ev.count;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   list_events_body(clips, nclips, t, worklist, n, base, stride, dl, alpha, beta, n_out, ws, ev);
-  // The last block to finish advances the event count; every block has read
-  // the count above before taking its ticket, so no block sees the new value.
-  __shared__ bool last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const unsigned int done = atomicAdd(reinterpret_cast<unsigned int*>(ws.misc + 1), 1u);
-    last = done == gridDim.x - 1;
-  }
-  __syncthreads();
-  if (last && threadIdx.x == 0) {
-    *ev.count = base + count[1];
-    ws.misc[1] = 0;   // re-arm the ticket for the next launch
-    __threadfence();
-  }
+}
+
+// Advances the event count after list_events_kernel (which read it as its base).
+__global__ void advance_kernel(int64_t* __restrict__ ev_count, const int32_t* __restrict__ count) {
+  if (threadIdx.x == 0) *ev_count += count[1];
 }
 
 __device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, int t,
@@ -250,7 +240,7 @@ __device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, 
     const ClipDev& C = clips[cl];
     const int64_t p = it & 0xFFFFFFFFll;
     if (p >= C.HW || t >= C.T) continue;
-    const int64_t e = base + ws.seg_prefix[cl] + (i - ws.seg_start[cl]);
+    const int64_t e = base + i;
     const float d = dl[C.pix_off + p];
     if (e >= 0 && e < ev.capacity) {
       ev.x[e] = static_cast<int32_t>(p % C.W);
@@ -262,7 +252,7 @@ __device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, 
     C.st_alpha[p] = alpha[i];
     for (int f = 0; f < C.F; ++f) {
       C.st_beta[f * C.HW + p] = beta[(2 + f) * n_out + i];
-      C.st_xref[f * C.HW + p] = feat_at(C, t, f, p);
+      C.st_xref[f * C.HW + p] = feat_value(C, t, f, p);
     }
     C.st_tref[p] = t;
   }
@@ -285,7 +275,7 @@ init_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const float* _
   if (beta && C.st_beta)
     for (int f = 0; f < C.F; ++f) C.st_beta[f * C.HW + p] = beta[(2 + f) * n_out + i];
   if (C.st_xref)
-    for (int f = 0; f < C.F; ++f) C.st_xref[f * C.HW + p] = feat_at(C, t, f, p);
+    for (int f = 0; f < C.F; ++f) C.st_xref[f * C.HW + p] = feat_value(C, t, f, p);
   if (C.st_tref) C.st_tref[p] = t;
 }
 
@@ -300,17 +290,16 @@ hipError_t launch_log(const float* E, float* y, int64_t n, float eps, hipStream_
 }
 
 hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
-                               float* dl, const float* alpha, const Workspace& ws, int pad,
-                               int64_t* worklist, int32_t* count, const EventsDev* ev,
-                               hipStream_t s) {
+                               float* dl, const float* alpha, const Workspace& ws, int64_t* worklist,
+                               int32_t* count, const EventsDev* ev, hipStream_t s) {
+  int64_t* wl = mode == kFlagThreshold ? worklist : nullptr;
   hipLaunchKernelGGL(flag_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
-                     t, mode, dl, alpha, ws);
-  hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, clips, nclips, ws, pad,
-                     mode == kFlagThreshold ? worklist : nullptr, count,
-                     mode == kFlagThreshold ? nullptr : ev->count);
+                     t, mode, dl, alpha, ws, ev ? ev->count : nullptr);
+  const int direct = nblk <= kDirectPrefixBlocks ? 1 : 0;
+  if (!direct) hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, ws, nblk);
   EventsDev none{};
   hipLaunchKernelGGL(scatter_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
-                     t, mode, ws, worklist, ev ? *ev : none);
+                     t, mode, ws, direct, wl, wl ? count : nullptr, ev ? *ev : none);
   return hipGetLastError();
 }
 
@@ -323,6 +312,7 @@ hipError_t launch_list_events(const ClipDev* clips, int nclips, int t, const int
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(list_events_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, clips,
                      nclips, t, worklist, count, dl, alpha, beta, n_out, max_items, ws, ev);
+  hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, ev.count, count);
   return hipGetLastError();
 }
 

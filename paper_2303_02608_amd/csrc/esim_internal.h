@@ -41,10 +41,18 @@ struct Workspace {
   int64_t* boffset;        // [nblk] output offset of each block
   uint64_t* flags;         // [nblk][kWavesPerBlock] flag ballots
   uint64_t* pol;           // [nblk][kWavesPerBlock] positive-polarity ballots
-  int64_t* seg_start;      // [nclips] first work-list entry of each clip
-  int64_t* seg_prefix;     // [nclips] flagged pixels of the clips before
-  int64_t* misc;           // [4] [0] event base of the last scan, [1] block ticket
+  int64_t* misc;           // [4] [0] event base of the current step
 };
+
+// Stored feature value f of pixel p at frame t (FP16 storage converted).
+__device__ __forceinline__ float feat_value(const ClipDev& C, int t, int f, int64_t p) {
+  const int64_t i = (static_cast<int64_t>(t) * C.F + f) * C.HW + p;
+  if (C.feat_f16) {
+    const uint16_t h = static_cast<const uint16_t*>(C.feat)[i];
+    return static_cast<float>(__builtin_bit_cast(_Float16, h));
+  }
+  return static_cast<const float*>(C.feat)[i];
+}
 
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t make_rsrc(const void* base, uint64_t bytes) {
   const uint32_t n = bytes >= 0xFFFFFFFFull ? 0xFFFFFFFFu : static_cast<uint32_t>(bytes);
@@ -128,14 +136,25 @@ struct RegressArgs {
   int64_t n_dense_groups;   // dense: wave-groups over all clips (for the chosen L)
   int64_t max_groups;       // upper bound of groups (grid sizing)
   int64_t n_out;
-  float* alpha;
+  float* alpha;             // nullable when update_state is set
   float* beta;
   float* resid;
   float* kappa;
+  int32_t update_state;     // write each item's model into its clip state (Sec. 2.2)
 };
 
 // Regression launcher: picks the kernel instance for (F, dtype, precision)
 // and the lanes-per-item L; returns hipSuccess or the launch error.
+using KernelFn = void (*)(RegressArgs);
+
+// Regression kernels of one feature count: general [lanes 2, 4, 8, 16][f16],
+// one-pass [f16], compensated FP32 [lanes 4, 16][f16] (null where not compiled).
+struct RegressTable {
+  KernelFn general[4][2] = {};
+  KernelFn onepass[2] = {};
+  KernelFn c32[2][2] = {};
+};
+
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
                           int blocks_per_cu, int max_r, hipStream_t s);
 int regress_supported_lanes(int F);

@@ -1,0 +1,234 @@
+// Weighted local regression (Sec. 2.1, eqs. 3-5) on gfx950: kernel templates.
+// Each feature count is instantiated in a translation unit of its own
+// (esim_regress_inst.hip); esim_regress.hip dispatches.
+//
+// One regression ("item") is the minimiser of
+//     (1/W) sum_i w_i (y_i - alpha - beta^T u_i)^2 + ridge * |beta|^2,
+//     u_i = x^i - x^c,  w_i = exp(-1/2 sum_j (u_ij / (h b_j))^2),  W = sum_i w_i,
+// over the window |dx|, |dy| <= r, |dt| <= tr (truncated at image borders and
+// clip ends), with x = (px / r, py / r, f_0 .. f_{F-1}).
+//
+// Mapping.  A wave holds G = 64 / L items; the L lanes of an item split the
+// 2r+1 window columns, so for one column pass the coordinate regressor is
+// constant in a lane and every Gram entry that involves it is folded once per
+// pass instead of once per sample (esim_wlr.h).  Loads are raw buffer loads
+// (SGPR resource + VGPR offset, the channel stride in the SGPR offset),
+// coalesced over the L adjacent columns of an item and over the G adjacent
+// items of a dense wave.
+//
+// Precision.  The weight exponent is summed in FP64 from FP64 differences of
+// the FP32 inputs and exponentiated with the FP32 hardware exp2 (about 1e-7
+// relative).  Gram, right-hand side and Cholesky are FP64: without packed FP32
+// (disabled in this build) an FP64 FMA issues at the same rate as an FP32 one
+// on CDNA4, and the windows are ill-conditioned (kappa up to ~1e6 with a
+// 1e-6 ridge), which FP32 accumulation does not survive at the 1e-4 contract.
+//
+// After the window loop the L lane partials are summed with DPP, every lane of
+// the item factors the (F+3)x(F+3) system redundantly (registers only) and the
+// lanes share the output writes.  The optional condition output is Hager's
+// 1-norm estimate on the factor.
+#pragma once
+#include <type_traits>
+
+#include "esim_wlr.h"
+
+namespace esim {
+namespace {
+
+// One group of a launch: G = 64 / L items, item0 + g * G + slot for the lane's
+// slot, below n_items (work lists) or the pixels of group g (dense).
+//
+// C32 selects the reduced-precision variant: FP32 regressors and weights,
+// FP32 Gram with block-compensated sums (GramC), FP32 Cholesky, and an FP64
+// re-solve of the same compensated Gram for items whose Hager condition
+// estimate exceeds kappa_fp64.  ONE selects the one-pass Gram (every lane
+// owns one window column).
+template <int F, int L, bool F16, bool C32, bool ONE>
+__device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, int64_t n_items,
+                                              int64_t item0) {
+  constexpr int D = F + 2;
+  constexpr int P = F + 3;
+  constexpr int G = kWave / L;
+  using Real = typename std::conditional<C32, float, double>::type;
+
+  const int lane = threadIdx.x & (kWave - 1);
+  const int slot = lane / L;
+  const int j = lane % L;
+  {
+    // ---- which item, clip, pixel and frame this lane group works on.  Items
+    //      are bounds-checked (clip, pixel, frame); invalid ones are skipped.
+    int my_cl = 0;
+    int64_t my_pix = 0, idx_out = 0;
+    int my_t = a.t;
+    bool valid = false;
+    if (a.items) {
+      const int64_t i = item0 + g * G + slot;
+      const int64_t it = i < n_items ? a.items[i] : -1;
+      if (it >= 0) {
+        const int c = item_clip(it);
+        if (c < a.nclips) {
+          const int64_t p = item_pixel(it);
+          const int fr = a.t >= 0 ? a.t : item_frame(it);
+          if (p < a.clips[c].HW && fr >= 0 && fr < a.clips[c].T) {
+            valid = true;
+            my_cl = c;
+            my_pix = p;
+            my_t = fr;
+          }
+        }
+      }
+      idx_out = i;
+    } else {
+      for (int c = 1; c < a.nclips; ++c)
+        if (a.clips[c].grp_off[lanes_index(L)] <= g) my_cl = c;
+      const int64_t p = (g - a.clips[my_cl].grp_off[lanes_index(L)]) * G + slot;
+      valid = p < a.clips[my_cl].HW && a.t < a.clips[my_cl].T;
+      my_pix = valid ? p : 0;
+      idx_out = a.clips[my_cl].pix_off + p;
+    }
+    // Waterfall over the clips present in the wave (one round when the work
+    // list keeps each wave inside one clip, as the threshold call does).
+    uint64_t todo = __ballot(valid);
+    while (todo != 0) {
+      const int cl = __builtin_amdgcn_readfirstlane(
+          __shfl(my_cl, __ffsll(static_cast<unsigned long long>(todo)) - 1));
+      const bool active = valid && my_cl == cl && ((todo >> lane) & 1ull);
+      todo &= ~__ballot(active);
+      const ClipDev& C = a.clips[cl];
+      // frames held by the buffer resources: the window of a uniform frame, or
+      // the whole clip when items carry their own frame
+      const int f0 = a.t >= 0 ? max(0, a.t - C.tr) : 0;
+      const int f1 = a.t >= 0 ? min(C.T, a.t + C.tr + 1) : C.T;
+      // inactive lanes read a valid centre pixel of the resource window
+      ItemGeom<F, F16, Real> geo;
+      make_geom(geo, C, active ? my_pix : 0, active ? my_t : (a.t >= 0 ? a.t : 0), f0, f1, active);
+
+      double th[P], rhs[P], Syy, iW, kap = 0.0;
+      if constexpr (!C32) {
+        Gram<F, double> gm;
+        if constexpr (ONE) {
+          // every lane owns one column (2r + 1 <= L, checked by the launcher)
+          gm.zero_onepass();
+          window_loop<F, L, F16, double>(
+              geo, j, [&](double) {},
+              [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+                gm.add_onepass(w, yd, v, vy);
+              },
+              [&](double vx) { gm.fold_onepass(vx); });
+        } else {
+          gm.zero();
+          window_loop<F, L, F16, double>(
+              geo, j, [&](double) { gm.pass_begin(); },
+              [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+                gm.add(w, yd, v, vy);
+              },
+              [&](double vx) { gm.pass_end(vx); });
+        }
+        gm.template lane_sum<L>();
+        double M[P * (P + 1) / 2], anorm;
+        iW = gram_solve<F, double>(gm, C, M, rhs, th, anorm);
+        Syy = gm.Syy;
+        // the one-pass instances leave the estimate to the general ones (the
+        // launcher never picks them when kappa is requested), which keeps
+        // their register budget within two waves per SIMD
+        if constexpr (!ONE) {
+          if (a.kappa) kap = anorm * hager_inv_norm1<P, double>(M);
+        } else {
+          (void)anorm;
+        }
+      } else {
+        GramC<F> gc;
+        gc.zero();
+        window_loop<F, L, F16, float>(
+            geo, j, [&](float) { gc.pass_begin(); },
+            [&](float w, float yd, const float (&v)[F], float vy, int, int, int, bool) {
+              gc.add(w, yd, v, vy);
+            },
+            [&](float vx) { gc.pass_end(vx); });
+        gc.template lane_sum<L>();
+        Gram<F, float> g32;
+        gc.values(g32);
+        float M32[P * (P + 1) / 2], r32[P], t32[P], an32;
+        iW = gram_solve<F, float>(g32, C, M32, r32, t32, an32);
+        kap = static_cast<double>(an32) * static_cast<double>(hager_inv_norm1<P, float>(M32));
+        const bool fallback = !(kap <= C.kappa_fp64);
+        Syy = g32.Syy;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+          th[i] = t32[i];
+          rhs[i] = r32[i];
+        }
+        if (__ballot(fallback && active) != 0) {
+          Gram<F, double> g64;
+          gc.values(g64);
+          double M[P * (P + 1) / 2], r64[P], t64[P], an64;
+          const double iW64 = gram_solve<F, double>(g64, C, M, r64, t64, an64);
+          if (fallback) {
+            iW = iW64;
+            Syy = g64.Syy;
+#pragma unroll
+            for (int i = 0; i < P; ++i) {
+              th[i] = t64[i];
+              rhs[i] = r64[i];
+            }
+          }
+        }
+      }
+
+      // ---- outputs (the lanes of an item share the writes)
+      if (active && a.update_state) {
+        // the pixel's reference model becomes this frame's: alpha, beta over
+        // the buffer channels, the feature vector and the frame (the values
+        // the event call would store from the outputs)
+        if (j == 0) {
+          C.st_alpha[my_pix] = static_cast<float>(th[0]);
+          C.st_tref[my_pix] = my_t;
+        }
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+          if (f % L == j) {
+            C.st_beta[f * C.HW + my_pix] = static_cast<float>(th[3 + f] * C.sf[2 + f]);
+            C.st_xref[f * C.HW + my_pix] = feat_value(C, my_t, f, my_pix);
+          }
+      }
+      if (active && a.alpha) {
+        if (j == 0) {
+          a.alpha[idx_out] = static_cast<float>(th[0]);
+          if (a.resid) {
+            // at the solution (A + Lambda) theta = rhs, so
+            // R = Syy/W - theta^T rhs - theta^T Lambda theta
+            double tg = 0.0, bb = 0.0;
+#pragma unroll
+            for (int i = 0; i < P; ++i) tg = fma(th[i], rhs[i], tg);
+#pragma unroll
+            for (int i = 1; i < P; ++i) bb = fma(th[i] * C.c2[i - 1], th[i], bb);
+            a.resid[idx_out] = static_cast<float>(Syy * iW - tg - C.ridge * bb);
+          }
+          if (a.kappa) a.kappa[idx_out] = static_cast<float>(kap);
+        }
+        if (a.beta) {
+#pragma unroll
+          for (int d = 0; d < D; ++d)
+            if (d % L == j)
+              a.beta[static_cast<int64_t>(d) * a.n_out + idx_out] = static_cast<float>(th[1 + d] * C.sf[d]);
+        }
+      }
+    }  // waterfall
+  }
+}
+
+template <int F, int L, bool F16, bool C32, bool ONE = false>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ONE ? 2 : 1)))
+regress_kernel(RegressArgs a) {
+  constexpr int G = kWave / L;
+  // the device count is clamped to the output length: item i writes index i
+  const int64_t n_items =
+      a.items ? max(static_cast<int64_t>(0), min(static_cast<int64_t>(a.count[0]), a.n_out)) : 0;
+  const int64_t ngroups = a.items ? (n_items + G - 1) / G : a.n_dense_groups;
+  GroupIter it(ngroups);
+  int64_t g;
+  while (it.next(g)) regress_group<F, L, F16, C32, ONE>(a, g, n_items, 0);
+}
+
+}  // namespace
+}  // namespace esim

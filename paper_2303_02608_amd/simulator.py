@@ -10,7 +10,11 @@ Three conversions of a clip (y = log brightness [T][H][W], feat [T][F][H][W]):
 * ``"raw"`` -- ESIM on the noisy frames (Sec. 3): eq. (1) on y.
 
 Every step is a libesim call enqueued on one stream; the loop never
-synchronises, so it can be captured in a hipGraph and replayed.
+synchronises, so it can be captured in a hipGraph and replayed.  By default a
+frame is one esim_step call (threshold, compaction with the events, and the
+list regression writing the state: three launches); ``fused=False`` runs the
+same frame through the separate threshold / regress / events calls, which also
+leave the work list and the regression outputs in this object's buffers.
 """
 from __future__ import annotations
 
@@ -46,11 +50,21 @@ class Simulator:
         self.graph_mode = None
 
     # -- one conversion, enqueued on the current stream --------------------
-    def enqueue(self, mode: str = "thresholded", record_flags: bool = False):
+    def enqueue(self, mode: str = "thresholded", record_flags: bool = False, fused: bool = True):
         if mode not in MODES:
             raise ValueError(mode)
         p, n = self.plan, self.HW
         self.ev.count.zero_()
+        if fused and not record_flags:
+            if mode == "thresholded":
+                B.step(p, 0, B.INIT)
+                for t in range(1, self.T):
+                    B.step(p, t, B.THRESHOLDED, self.ev, self.dl)
+            else:
+                m = B.EXHAUSTIVE if mode == "exhaustive" else B.RAW
+                for t in range(self.T):
+                    B.step(p, t, m, self.ev, self.dl)
+            return
         if mode == "thresholded":
             B.regress(p, 0, None, None, n, self.alpha, self.beta)
             B.events(p, 0, B.INIT, None, alpha=self.alpha, beta=self.beta, n_out=n)
@@ -69,25 +83,25 @@ class Simulator:
             for t in range(self.T):
                 B.events(p, t, B.RAW, self.ev, dl=self.dl)
 
-    def capture(self, mode: str = "thresholded"):
+    def capture(self, mode: str = "thresholded", fused: bool = True):
         """Record one conversion into a hipGraph (torch.cuda.CUDAGraph)."""
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self.enqueue(mode)          # warm-up outside the graph
+            self.enqueue(mode, fused=fused)          # warm-up outside the graph
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.enqueue(mode)
+            self.enqueue(mode, fused=fused)
         self.graph, self.graph_mode = g, mode
         return g
 
     def replay(self):
         self.graph.replay()
 
-    def run(self, mode: str = "thresholded"):
-        self.enqueue(mode)
+    def run(self, mode: str = "thresholded", fused: bool = True):
+        self.enqueue(mode, fused=fused)
         torch.cuda.synchronize()
         return self.events()
 
@@ -116,9 +130,14 @@ class BatchSimulator:
             capacity = min(sum(int(f.shape[0]) * f.shape[2] * f.shape[3] for f in feats), 1 << 27)
         self.ev = B.Events(capacity, dev, with_clip=True)
 
-    def enqueue(self):
+    def enqueue(self, fused: bool = True):
         p, n = self.plan, self.n_out
         self.ev.count.zero_()
+        if fused:
+            B.step(p, 0, B.INIT)
+            for t in range(1, self.T):
+                B.step(p, t, B.THRESHOLDED, self.ev, self.dl)
+            return
         B.regress(p, 0, None, None, n, self.alpha, self.beta)
         B.events(p, 0, B.INIT, None, alpha=self.alpha, beta=self.beta, n_out=n)
         for t in range(1, self.T):
@@ -127,20 +146,20 @@ class BatchSimulator:
             B.events(p, t, B.THRESHOLDED, self.ev, worklist=self.worklist, count=self.count,
                      dl=self.dl, alpha=self.alpha, beta=self.beta, n_out=n)
 
-    def capture(self):
+    def capture(self, fused: bool = True):
         s = torch.cuda.Stream()
         s.wait_stream(torch.cuda.current_stream())
         with torch.cuda.stream(s):
-            self.enqueue()
+            self.enqueue(fused)
         torch.cuda.current_stream().wait_stream(s)
         torch.cuda.synchronize()
         g = torch.cuda.CUDAGraph()
         with torch.cuda.graph(g):
-            self.enqueue()
+            self.enqueue(fused)
         self.graph = g
         return g
 
-    def run(self):
-        self.enqueue()
+    def run(self, fused: bool = True):
+        self.enqueue(fused)
         torch.cuda.synchronize()
         return self.ev.host()

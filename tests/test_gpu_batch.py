@@ -38,6 +38,10 @@ def test_batch_equals_single_clips_and_oracle():
         bs.plan.set_schedule(*sched)
         got = bs.run()
         assert got["count"] > 0
+        # one esim_step per frame == separate threshold / regress / events calls
+        sep = bs.run(fused=False)
+        for k in ("x", "y", "t", "p", "clip"):
+            assert np.array_equal(got[k], sep[k]), (sched, k)
         for c, ((E, feat, p), (y, fd)) in enumerate(zip(clips, devs)):
             m = got["clip"] == c
             single = Simulator(y, fd, p).run("thresholded")

@@ -196,3 +196,27 @@ def test_resume_from_saved_state(small_clip):
     for key in ("x", "y", "t", "p"):
         assert np.array_equal(got[key], full[key][m])
     del s2
+
+
+@pytest.mark.parametrize("mode", ["thresholded", "exhaustive", "raw"])
+def test_step_matches_separate_calls(small_clip, mode):
+    """esim_step (threshold + compaction with events + regression writing the
+    state) gives bit-for-bit the events, state and dl of the separate
+    threshold / regress / events calls."""
+    E, feat, cfg = small_clip["E"], small_clip["feat"], small_clip["cfg"]
+    p = _params(cfg)
+    say(f"step vs separate calls, {mode}")
+    y, fd = to_dev(E, feat)
+    a = Simulator(y, fd, p)
+    b = Simulator(y, fd, p)
+    a.enqueue(mode, fused=True)
+    b.enqueue(mode, fused=False)
+    torch.cuda.synchronize()
+    ea, eb = a.events(), b.events()
+    assert ea["count"] == eb["count"] > 0
+    for k in ("x", "y", "t", "p"):
+        assert np.array_equal(ea[k], eb[k]), k
+    names = ("alpha", "beta", "xref", "tref") if mode == "thresholded" else ("alpha",)
+    for n in names:
+        assert torch.equal(getattr(a.state, n), getattr(b.state, n)), n
+    assert torch.equal(a.dl, b.dl)

@@ -196,3 +196,4 @@ def test_regress_is_deterministic(small_clip):
     a2 = _regress_all(small_clip["E"], small_clip["feat"], p, 4)
     for u, v in zip(a1, a2):
         assert np.array_equal(u.view(np.uint32), v.view(np.uint32))
+
