@@ -144,8 +144,9 @@ int64_t esim_plan_pixel_offset(esim_plan plan, int32_t c);
 
 /* Schedule of the regression kernel (set by the autotuner, or by hand): the
  * lanes that share one regression item in dense launches and in work-list
- * launches (2, 4, 8 or 16; more lanes = more, shorter wave tasks for sparse
- * lists) and the persistent blocks per CU (1..64).  Defaults 4, 16, 4.
+ * launches (1, 2, 4, 8 or 16; more lanes = more, shorter wave tasks for sparse
+ * lists) and the persistent blocks per CU (1..64).  Defaults 1, 16, 4 (4, 16, 4 with
+ * ESIM_GRAM_F32C).
  * Errors: E_UNSUPPORTED (lanes not compiled), E_INVAL. */
 int esim_plan_set_schedule(esim_plan plan, int32_t lanes_dense, int32_t lanes_list,
                            int32_t blocks_per_cu);

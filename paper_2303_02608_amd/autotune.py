@@ -4,8 +4,8 @@ The regression kernel has two schedule knobs per plan (esim_plan_set_schedule):
 the number of lanes that share one regression item (dense launches and
 work-list launches separately) and the persistent blocks per CU.  More lanes
 per item means more, shorter wave tasks, which pays off for the sparse per-frame
-work lists of the thresholded path; dense launches prefer fewer lanes (less
-cross-lane reduction).
+work lists of the thresholded path; dense launches prefer fewer lanes (no
+cross-lane reduction, no idle column lanes, the solve shared by 64 items).
 
 The tuner replays a short prefix of the real conversion (frame 0 dense, then a
 few thresholded frames) once per candidate and times only the regression
@@ -60,7 +60,7 @@ def _time_prefix(plan: B.Plan, frames: int, bufs) -> Tuple[float, float]:
     return dense, lst
 
 
-def tune(plan: B.Plan, frames: int = 12, lanes_dense: Iterable[int] = (2, 4, 8),
+def tune(plan: B.Plan, frames: int = 12, lanes_dense: Iterable[int] = (1, 2, 4),
          lanes_list: Iterable[int] = (4, 8, 16), blocks_per_cu: Iterable[int] = (1, 2, 4, 8),
          reps: int = 2, verbose: bool = False) -> Tuple[int, int, int]:
     """Pick (lanes_dense, lanes_list, blocks_per_cu) for the plan and apply it.
@@ -82,8 +82,8 @@ def tune(plan: B.Plan, frames: int = 12, lanes_dense: Iterable[int] = (2, 4, 8),
     best_dense: Dict[int, float] = {}
     best_list: Dict[Tuple[int, int], float] = {}
     for ld, ll, bpc in itertools.product(lanes_dense, lanes_list, blocks_per_cu):
-        if ld != 4 and ll != 16:
-            continue          # lanes_dense is tuned along one line only
+        if ld != 1 and ll != 16:
+            continue          # tuned along the lines through (1, 16) only
         try:
             plan.set_schedule(ld, ll, bpc)
         except B.EsimError:

@@ -23,7 +23,7 @@ struct esim_plan_s {
   int64_t nblk = 0;
   int64_t wl_capacity = 0;
   int64_t dense_groups[5] = {0, 0, 0, 0, 0};
-  int lanes_dense = 4;     // lanes per regression item, dense launches
+  int lanes_dense = 1;     // lanes per regression item, dense launches
   int lanes_list = 16;     // lanes per regression item, work-list launches
   int blocks_per_cu = 4;   // persistent grid: 256 CUs x this many blocks
   uint64_t max_feat_bytes = 0;
@@ -110,7 +110,7 @@ const char* esim_status_string(int s) {
 const char* esim_last_error(void) { return g_last_error.c_str(); }
 
 const char* esim_build_info(void) {
-  return "libesim gfx950; regress: F=1..12 x lanes{2,4,8,16} x {f32,f16} features, FP64 Gram; "
+  return "libesim gfx950; regress: F=1..12 x lanes{1,2,4,8,16} x {f32,f16} features, FP64 Gram; "
          "compensated FP32 Gram for F in {7,10} x lanes {4,16}";
 }
 
@@ -217,6 +217,8 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       pl->max_feat_bytes = std::max(pl->max_feat_bytes, fb);
       pl->host.push_back(cd);
     }
+    // the compensated-FP32 instances exist for 4 and 16 lanes only
+    if (params[0].precision == ESIM_GRAM_F32C) pl->lanes_dense = 4;
     pl->npix = pix;
     pl->nblk = blk;
     pl->wl_capacity = wl;
@@ -458,7 +460,7 @@ int esim_wlr_backward(esim_plan pl, const int64_t* items, int64_t n, const float
 }
 
 // Schedule override used by the autotuner: lanes per item for dense and for
-// work-list launches (2, 4, 8, 16) and persistent blocks per CU.  Not part of
+// work-list launches (1, 2, 4, 8, 16) and persistent blocks per CU.  Not part of
 // the hot path.
 int esim_plan_set_schedule(esim_plan pl, int32_t lanes_dense, int32_t lanes_list,
                            int32_t blocks_per_cu) {

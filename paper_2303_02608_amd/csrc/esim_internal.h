@@ -147,10 +147,10 @@ struct RegressArgs {
 // and the lanes-per-item L; returns hipSuccess or the launch error.
 using KernelFn = void (*)(RegressArgs);
 
-// Regression kernels of one feature count: general [lanes 2, 4, 8, 16][f16],
+// Regression kernels of one feature count: general [lanes 1, 2, 4, 8, 16][f16],
 // one-pass [f16], compensated FP32 [lanes 4, 16][f16] (null where not compiled).
 struct RegressTable {
-  KernelFn general[4][2] = {};
+  KernelFn general[5][2] = {};
   KernelFn onepass[2] = {};
   KernelFn c32[2][2] = {};
 };

@@ -36,7 +36,7 @@ const RegressTable* table(int F) {
 
 KernelFn pick(int F, int lanes, bool f16) {
   const RegressTable* t = table(F);
-  const int li = lanes == 2 ? 0 : lanes == 4 ? 1 : lanes == 8 ? 2 : lanes == 16 ? 3 : -1;
+  const int li = lanes == 1 ? 0 : lanes == 2 ? 1 : lanes == 4 ? 2 : lanes == 8 ? 3 : lanes == 16 ? 4 : -1;
   return (t && li >= 0) ? t->general[li][f16] : nullptr;
 }
 
@@ -53,7 +53,7 @@ KernelFn pick_c32(int F, int lanes, bool f16) {
 
 }  // namespace
 
-int regress_supported_lanes(int F) { return (F >= 1 && F <= ESIM_MAX_F) ? 0x2 | 0x4 | 0x8 | 0x10 : 0; }
+int regress_supported_lanes(int F) { return (F >= 1 && F <= ESIM_MAX_F) ? 0x1 | 0x2 | 0x4 | 0x8 | 0x10 : 0; }
 
 bool regress_supports(int F, int lanes, int precision) {
   if (precision == ESIM_GRAM_F32C) return pick_c32(F, lanes, false) != nullptr;

@@ -116,13 +116,13 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
               },
               [&](double vx) { gm.fold_onepass(vx); });
         } else {
-          gm.zero();
+          gm.zero_snap();
           window_loop<F, L, F16, double>(
-              geo, j, [&](double) { gm.pass_begin(); },
+              geo, j, [&](double) { gm.pass_begin_snap(); },
               [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-                gm.add(w, yd, v, vy);
+                gm.add_onepass(w, yd, v, vy);
               },
-              [&](double vx) { gm.pass_end(vx); });
+              [&](double vx) { gm.pass_end_snap(vx); });
         }
         gm.template lane_sum<L>();
         double M[P * (P + 1) / 2], anorm;
@@ -217,8 +217,17 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
   }
 }
 
+// FP64 instances up to 8 features keep their window-loop accumulators within
+// half the register file and run two waves per SIMD (a wave's scalar and
+// memory instructions then issue beside the other wave's FMAs); larger F, and
+// the compensated-FP32 variant, run one.
+template <int F, bool C32>
+constexpr int regress_waves_per_simd() {
+  return (!C32 && F <= 8) ? 2 : 1;
+}
+
 template <int F, int L, bool F16, bool C32, bool ONE = false>
-__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ONE ? 2 : 1)))
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(regress_waves_per_simd<F, C32>())))
 regress_kernel(RegressArgs a) {
   constexpr int G = kWave / L;
   // the device count is clamped to the output length: item i writes index i

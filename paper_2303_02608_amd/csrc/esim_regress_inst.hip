@@ -13,14 +13,16 @@ namespace esim {
 
 void ESIM_CAT(regress_table_, ESIM_REGRESS_F)(RegressTable& t) {
   constexpr int F = ESIM_REGRESS_F;
-  t.general[0][0] = regress_kernel<F, 2, false, false>;
-  t.general[0][1] = regress_kernel<F, 2, true, false>;
-  t.general[1][0] = regress_kernel<F, 4, false, false>;
-  t.general[1][1] = regress_kernel<F, 4, true, false>;
-  t.general[2][0] = regress_kernel<F, 8, false, false>;
-  t.general[2][1] = regress_kernel<F, 8, true, false>;
-  t.general[3][0] = regress_kernel<F, 16, false, false>;
-  t.general[3][1] = regress_kernel<F, 16, true, false>;
+  t.general[0][0] = regress_kernel<F, 1, false, false>;
+  t.general[0][1] = regress_kernel<F, 1, true, false>;
+  t.general[1][0] = regress_kernel<F, 2, false, false>;
+  t.general[1][1] = regress_kernel<F, 2, true, false>;
+  t.general[2][0] = regress_kernel<F, 4, false, false>;
+  t.general[2][1] = regress_kernel<F, 4, true, false>;
+  t.general[3][0] = regress_kernel<F, 8, false, false>;
+  t.general[3][1] = regress_kernel<F, 8, true, false>;
+  t.general[4][0] = regress_kernel<F, 16, false, false>;
+  t.general[4][1] = regress_kernel<F, 16, true, false>;
   t.onepass[0] = regress_kernel<F, 16, false, false, true>;
   t.onepass[1] = regress_kernel<F, 16, true, false, true>;
   // the compensated-FP32 variant is compiled for the feature counts of the

@@ -272,6 +272,35 @@ struct Gram {
 #pragma unroll
     for (int f = 0; f < F; ++f) Axf[f] = vx * A0f[f];
   }
+  // Pass-snapshot form: the window loop accumulates as the one-pass form; at
+  // each pass start the first-row totals (W, v_y, y and feature sums) are
+  // copied, and at its end the entries with a v_x factor take v_x times the
+  // pass's increment of them.  The snapshot and the v_x entries are only
+  // touched once per pass, so the loop's live accumulators are the one-pass
+  // ones.  (The increment is a difference of two FP64 totals of at most
+  // 2r + 1 passes: its rounding is of the order of the totals' own.)
+  __device__ __forceinline__ void zero_snap() {
+    zero_onepass();
+    A0x = Axx = Axy = gx = 0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) Axf[f] = 0;
+  }
+  __device__ __forceinline__ void pass_begin_snap() {
+    qW = SW;
+    qY = A0y;
+    qG = g0;
+#pragma unroll
+    for (int f = 0; f < F; ++f) qF[f] = A0f[f];
+  }
+  __device__ __forceinline__ void pass_end_snap(Real vx) {
+    const Real dW = SW - qW;
+    A0x = fma(vx, dW, A0x);
+    Axx = fma(vx * vx, dW, Axx);
+    Axy = fma(vx, A0y - qY, Axy);
+    gx = fma(vx, g0 - qG, gx);
+#pragma unroll
+    for (int f = 0; f < F; ++f) Axf[f] = fma(vx, A0f[f] - qF[f], Axf[f]);
+  }
   // Applies one DPP butterfly step to every total; the steps run in sequence
   // over all totals (step-major), so consecutive DPP reads never depend on
   // the previous instruction.

@@ -109,7 +109,7 @@ def test_dense_regress_shapes(W, H, T, F, r, tr, t, ridge, seed):
     _check(*out, ref, f"shape {W}x{H} F={F} r={r}", kappa1=_kappa1(E, feat, p, t))
 
 
-@pytest.mark.parametrize("lanes", [2, 4, 8, 16])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16])
 def test_lanes_per_item_variants(small_clip, lanes):
     cfg = small_clip["cfg"]
     p = B.Params(r=cfg["r"], tr=1, C=cfg["C"], h=1.3, b=[1.0, 0.8, 1.2, 1.1, 0.9, 1.0, 0.7, 1.5, 1.0])
