@@ -10,8 +10,10 @@
 //
 // Mapping.  A wave holds G = 64 / L items; the L lanes of an item split the
 // 2r+1 window columns, so for one column pass the coordinate regressor is
-// constant in a lane and every Gram entry that involves it is folded once per
-// pass instead of once per sample (esim_wlr.h).  Loads are raw buffer loads
+// constant in a lane and every Gram entry that involves it is formed once per
+// pass instead of once per sample (esim_wlr.h).  Dense launches use L = 1
+// (64 items per wave, no cross-lane sums), work lists L = 16 (4 items per
+// wave, one column per lane).  Loads are raw buffer loads
 // (SGPR resource + VGPR offset, the channel stride in the SGPR offset),
 // coalesced over the L adjacent columns of an item and over the G adjacent
 // items of a dense wave.
@@ -35,8 +37,8 @@
 namespace esim {
 namespace {
 
-// One group of a launch: G = 64 / L items, item0 + g * G + slot for the lane's
-// slot, below n_items (work lists) or the pixels of group g (dense).
+// One group of a launch: G = 64 / L items, g * G + slot for the lane's slot,
+// below n_items (work lists) or the pixels of group g (dense).
 //
 // C32 selects the reduced-precision variant: FP32 regressors and weights,
 // FP32 Gram with block-compensated sums (GramC), FP32 Cholesky, and an FP64
@@ -44,8 +46,7 @@ namespace {
 // estimate exceeds kappa_fp64.  ONE selects the one-pass Gram (every lane
 // owns one window column).
 template <int F, int L, bool F16, bool C32, bool ONE>
-__device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, int64_t n_items,
-                                              int64_t item0) {
+__device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, int64_t n_items) {
   constexpr int D = F + 2;
   constexpr int P = F + 3;
   constexpr int G = kWave / L;
@@ -62,7 +63,7 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
     int my_t = a.t;
     bool valid = false;
     if (a.items) {
-      const int64_t i = item0 + g * G + slot;
+      const int64_t i = g * G + slot;
       const int64_t it = i < n_items ? a.items[i] : -1;
       if (it >= 0) {
         const int c = item_clip(it);
@@ -236,7 +237,7 @@ regress_kernel(RegressArgs a) {
   const int64_t ngroups = a.items ? (n_items + G - 1) / G : a.n_dense_groups;
   GroupIter it(ngroups);
   int64_t g;
-  while (it.next(g)) regress_group<F, L, F16, C32, ONE>(a, g, n_items, 0);
+  while (it.next(g)) regress_group<F, L, F16, C32, ONE>(a, g, n_items);
 }
 
 }  // namespace

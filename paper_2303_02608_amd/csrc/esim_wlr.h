@@ -8,9 +8,9 @@
 //
 // The L lanes of an item split the window columns (lane j takes dx = -r + j,
 // -r + j + L, ...); for one column pass v_x is constant in the lane.  The rows
-// (dt, dy) of a column are streamed through two register buffers so the loads
-// of one row are in flight while the other row is used.  Rows outside the
-// image (or past the last row) read the valid centre pixel and get weight 0.
+// (dt, dy) of a column are software-pipelined in registers (window_loop): the
+// loads of a row are issued two rows ahead of its use.  Rows outside the image
+// (or past the last row) read the valid centre pixel and get weight 0.
 #pragma once
 
 #include "esim_internal.h"
