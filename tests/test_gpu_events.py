@@ -220,3 +220,55 @@ def test_step_matches_separate_calls(small_clip, mode):
     for n in names:
         assert torch.equal(getattr(a.state, n), getattr(b.state, n)), n
     assert torch.equal(a.dl, b.dl)
+
+
+def test_large_frame_compaction_uses_scan_kernel():
+    """A frame of more than 4096 compaction blocks (1280x1024 = 5120) takes the
+    one-block scan kernel instead of the per-block prefix: raw-mode events
+    match the oracle exactly, and the step entry point matches the separate
+    calls in every mode."""
+    W, H, T, F = 1280, 1024, 3, 2
+    d = synth.random_features_clip(W, H, T, F, seed=21)
+    E, feat = d["E"].numpy(), d["feat"].numpy()
+    p = B.Params(r=2, tr=0, C=0.3)
+    say("large-frame compaction (scan kernel)")
+    gpu, sim = run_gpu(E, feat, p, "raw")
+    orc = oracle.run(oracle_clip(E, feat), oracle.Params(p.r, p.tr, p.C), MODE_ID["raw"])
+    assert gpu["count"] == orc["count"] > 10000
+    ox, oy, ot, op = orc["events"]
+    key = lambda t, y, x: (t.astype(np.int64) << 40) + y.astype(np.int64) * W + x
+    og = np.argsort(key(ot, oy, ox), kind="stable")
+    _assert_sorted(gpu, W)
+    assert np.array_equal(key(gpu["t"], gpu["y"], gpu["x"]), key(ot, oy, ox)[og])
+    assert np.array_equal(gpu["p"], op[og])
+    y, fd = to_dev(E, feat)
+    for mode in ("thresholded", "raw"):
+        a = Simulator(y, fd, p)
+        b = Simulator(y, fd, p)
+        a.enqueue(mode, fused=True)
+        b.enqueue(mode, fused=False)
+        torch.cuda.synchronize()
+        ea, eb = a.events(), b.events()
+        assert ea["count"] == eb["count"] > 0, mode
+        for k in ("x", "y", "t", "p"):
+            assert np.array_equal(ea[k], eb[k]), (mode, k)
+
+
+def test_step_without_dl(small_clip):
+    """esim_step with dl = NULL gives the same events as with a dl buffer."""
+    E, feat, cfg = small_clip["E"], small_clip["feat"], small_clip["cfg"]
+    p = _params(cfg)
+    say("step without dl")
+    y, fd = to_dev(E, feat)
+    a = Simulator(y, fd, p)
+    a.enqueue("thresholded")
+    b = Simulator(y, fd, p)
+    b.ev.count.zero_()
+    B.step(b.plan, 0, B.INIT)
+    for t in range(1, b.T):
+        B.step(b.plan, t, B.THRESHOLDED, b.ev, None)
+    torch.cuda.synchronize()
+    ea, eb = a.events(), b.events()
+    assert ea["count"] == eb["count"] > 0
+    for k in ("x", "y", "t", "p"):
+        assert np.array_equal(ea[k], eb[k])
