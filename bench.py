@@ -13,6 +13,14 @@ once in a hipGraph and replayed.  The exhaustive WLR+ESIM path is timed the
 same way on the same clip.  `value` is the thresholded path's pixel-frames/s
 (T*H*W per step); events/s are reported beside it.
 
+Other workloads (`--workload`, one JSON line each; the default is the DVS line
+above): `precision` (1920x1080, F = 10 FP16 features, r = 10, tr = 2: dense
+regression and a 24-frame thresholded conversion with the FP64 Gram and with
+the compensated-FP32 Gram), `batch` (the 32-clip batch, frames scaled down to
+about 2e8 pixel-frames: one batched plan against the clips converted one by
+one) and `diff` (640x480x60: forward regressions of the differentiation loss
+and their adjoint).
+
 Roofline: the dominant kernel is the regression.  Its launches are bracketed
 with HIP events on the launch stream during an instrumented eager pass of the
 same conversion; achieved = algorithmic FLOPs (per regression
@@ -78,6 +86,163 @@ def traffic_from_profile(launch_items):
     return d.get("bytes_per_launch")
 
 
+def _time_ms(fn, reps, warmup=1):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps
+
+
+def _graph(fn):
+    """Captures fn() (after one eager warm-up on a side stream) and returns the replay."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        fn()
+    return g.replay
+
+
+def workload_precision(args, B, synth, Simulator):
+    """X1: F = 10 FP16 features at 1920x1080, r = 10, tr = 2."""
+    import torch
+    from paper_2303_02608_amd import autotune
+    cfg = synth.config_spec(4)
+    spec = cfg["spec"]
+    T = 24
+    t0 = time.time()
+    d = synth.make_clip(spec, device="cuda", frames=range(T))
+    y = B.log_brightness(d["E"])
+    feat = d["feat"]
+    torch.cuda.synchronize()
+    log(f"generated {spec.W}x{spec.H}x{T} (of {spec.T}) F={spec.F} f16 in {time.time() - t0:.1f}s")
+    _, F, H, W = feat.shape
+    HW = H * W
+    r, tr, C = cfg["r"], cfg["tr"], cfg["C"]
+    tc = T // 2
+    om = omega_sizes(np.arange(HW) % W, np.arange(HW) // W, np.full(HW, tc), W, H, T, r, tr)
+    fl = regress_flops(om, F).sum()
+    out = {"workload": f"precision {W}x{H}, {T} of {spec.T} frames, F={F} f16, r={r}, tr={tr}, C={C}"}
+    alphas = {}
+    for name, prec, kb in (("fp64", B.GRAM_F64, float("inf")), ("f32c", B.GRAM_F32C, 1e6)):
+        p = B.Params(r=r, tr=tr, C=C, precision=prec, kappa_fp64=kb)
+        sim = Simulator(y, feat, p)
+        plan = sim.plan
+        sched = autotune.tune(plan)
+        a = torch.empty(HW, device="cuda")
+        b = torch.empty((plan.D, HW), device="cuda")
+        K = torch.empty(HW, device="cuda") if prec == B.GRAM_F32C else None
+        ms = _time_ms(lambda: B.regress(plan, tc, None, None, HW, a, b, None, K), 3)
+        alphas[name] = a.clone()
+        row = {"dense_regress_ms": round(ms, 3), "dense_tflops": round(fl / (ms * 1e-3) / 1e12, 2),
+               "dense_frac": round(fl / (ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS, 4),
+               "schedule": list(sched)}
+        if K is not None:
+            k = K.cpu().numpy()
+            row["fp64_resolve_share"] = round(float(np.mean(~(k <= kb))), 5)
+        run = _graph(lambda: sim.enqueue("thresholded"))
+        ms_t = _time_ms(run, 3)
+        ev = sim.events()
+        row.update(thresholded_ms=round(ms_t, 3), pixel_frames_per_s=round(T * HW / (ms_t * 1e-3), 1),
+                   events=ev["count"], events_per_s=round(ev["count"] / (ms_t * 1e-3), 1))
+        out[name] = row
+        log(f"precision {name}: dense {ms:.3f} ms, thresholded {ms_t:.3f} ms")
+        del sim
+    da = (alphas["f32c"] - alphas["fp64"]).abs() / alphas["fp64"].abs().clamp(min=1.0)
+    out["f32c_vs_fp64_alpha_rel_err_max"] = float(da.max())
+    return out
+
+
+def workload_batch(args, B, synth, Simulator):
+    """X2: the 32-clip batch, frames scaled to about 2e8 pixel-frames."""
+    import torch
+    from paper_2303_02608_amd.simulator import BatchSimulator
+    specs = synth.batch_specs(32, seed=5000, max_pixel_frames=2e8)
+    t0 = time.time()
+    ys, feats, params = [], [], []
+    for c in specs:
+        d = synth.make_clip(c["spec"], device="cuda")
+        ys.append(B.log_brightness(d["E"]))
+        feats.append(d["feat"])
+        params.append(B.Params(r=c["r"], tr=c["tr"], C=c["C"]))
+        del d
+    torch.cuda.synchronize()
+    pf = sum(int(f.shape[0]) * f.shape[2] * f.shape[3] for f in feats)
+    log(f"generated {len(specs)} clips, {pf / 1e6:.1f} M pixel-frames in {time.time() - t0:.1f}s")
+    bs = BatchSimulator(ys, feats, params)
+    run = _graph(bs.enqueue)
+    ms_b = _time_ms(run, 3)
+    ev_b = bs.ev.host()["count"]
+    sims = [Simulator(y, f, p) for y, f, p in zip(ys, feats, params)]
+    runs = [_graph(lambda s=s: s.enqueue("thresholded")) for s in sims]
+    ms_s = _time_ms(lambda: [r() for r in runs], 3)
+    ev_s = sum(s.events()["count"] for s in sims)
+    log(f"batch: {ms_b:.2f} ms batched, {ms_s:.2f} ms one by one")
+    return {"workload": f"batch of {len(specs)} clips, {pf} pixel-frames (frames scaled to 2e8)",
+            "batched_ms": round(ms_b, 3), "batched_pixel_frames_per_s": round(pf / (ms_b * 1e-3), 1),
+            "one_by_one_ms": round(ms_s, 3),
+            "one_by_one_pixel_frames_per_s": round(pf / (ms_s * 1e-3), 1),
+            "events": ev_b, "events_one_by_one": ev_s,
+            "batched_speedup": round(ms_s / ms_b, 3)}
+
+
+def workload_diff(args, B, synth, Simulator):
+    """X3: forward regressions of the differentiation loss and their adjoint."""
+    import torch
+    cfg = synth.config_spec(3)
+    spec = cfg["spec"]
+    t0 = time.time()
+    d = synth.make_clip(spec, device="cuda")
+    y = B.log_brightness(d["E"])
+    feat = d["feat"]
+    torch.cuda.synchronize()
+    log(f"generated {spec.W}x{spec.H}x{spec.T} in {time.time() - t0:.1f}s")
+    T, F, H, W = feat.shape
+    HW = H * W
+    r, tr, C = cfg["r"], cfg["tr"], cfg["C"]
+    p = B.Params(r=r, tr=tr, C=C)
+    ev = Simulator(y, feat, p).run("thresholded")
+    xs, ys_, ts = (ev[k].astype(np.int64) for k in ("x", "y", "t"))
+    items = np.concatenate([np.arange(HW, dtype=np.int64), (ts << 44) | (ys_ * W + xs)])
+    n = items.size
+    it = torch.from_numpy(items).cuda()
+    plan = B.Plan([y], [feat], [p])
+    alpha = torch.empty(n, device="cuda")
+    cnt = torch.tensor([n, n], dtype=torch.int32, device="cuda")
+    ms_f = _time_ms(lambda: B.regress(plan, -1, it, cnt, n, alpha), 3)
+    g_a = torch.ones(n, device="cuda")
+    g_y = torch.zeros_like(y)
+    g_b = torch.zeros(plan.D, dtype=torch.float64, device="cuda")
+    scratch = torch.empty(B.backward_scratch_bytes(plan, n), dtype=torch.uint8, device="cuda")
+    ms_b = _time_ms(lambda: B.backward(plan, it, g_a, g_y, g_b, scratch), 3)
+    tt = np.concatenate([np.zeros(HW, np.int64), ts])
+    px = np.concatenate([np.arange(HW) % W, xs])
+    py = np.concatenate([np.arange(HW) // W, ys_])
+    om = omega_sizes(px, py, tt, W, H, T, r, tr)
+    fl_f = regress_flops(om, F).sum()
+    fl_b = fl_f + 60.0 * om.sum()     # the adjoint recomputes the forward window, then ~60 FLOP/sample
+    log(f"diff: {n} regressions, forward {ms_f:.2f} ms, adjoint {ms_b:.2f} ms")
+    return {"workload": f"diff {W}x{H}x{T}, F={F}, r={r}, tr={tr}, C={C}",
+            "regressions": int(n), "forward_ms": round(ms_f, 3),
+            "forward_regressions_per_s": round(n / (ms_f * 1e-3), 1),
+            "forward_tflops": round(fl_f / (ms_f * 1e-3) / 1e12, 2),
+            "adjoint_ms": round(ms_b, 3), "adjoint_regressions_per_s": round(n / (ms_b * 1e-3), 1),
+            "adjoint_tflops": round(fl_b / (ms_b * 1e-3) / 1e12, 2),
+            "adjoint_flop_model": "forward F_reg + 60 FLOP per window sample"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +260,8 @@ def main():
                     help="load the clip saved by --save-clip instead of generating it")
     ap.add_argument("--schedule", type=str, default=None,
                     help="lanes_dense,lanes_list,blocks_per_cu (skips the autotuner)")
+    ap.add_argument("--workload", choices=("dvs", "precision", "batch", "diff"), default="dvs",
+                    help="dvs (default, the contract line) or one of the extension workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (the "
                          "known-size reference for HBM counter calibration)")
@@ -118,6 +285,13 @@ def main():
     B.load()   # raises if libesim.so is missing: there is no fallback
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.workload != "dvs":
+        fn = {"precision": workload_precision, "batch": workload_batch, "diff": workload_diff}
+        res = fn[args.workload](args, B, synth, Simulator)
+        res = {"metric": f"{args.workload} workload", "n_gpus": 1, "dtype": "f64",
+               "data": "synthetic", **res}
+        print(json.dumps(res), flush=True)
+        return
 
     cfg = synth.config_spec(1)
     spec = cfg["spec"]

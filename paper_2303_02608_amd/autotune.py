@@ -27,7 +27,7 @@ _cache: Dict[tuple, Tuple[int, int, int]] = {}
 def _key(plan: B.Plan, frames: int):
     parts = []
     for y, f, p in zip(plan.ys, plan.feats, plan.params):
-        parts.append((tuple(f.shape), str(f.dtype), p.r, p.tr, p.C))
+        parts.append((tuple(f.shape), str(f.dtype), p.r, p.tr, p.C, p.precision))
     return (tuple(parts), frames)
 
 

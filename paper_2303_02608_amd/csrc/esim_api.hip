@@ -29,6 +29,7 @@ struct esim_plan_s {
   uint64_t max_feat_bytes = 0;
   // work buffers of esim_step (allocated with the plan)
   void* step_mem = nullptr;
+  int64_t* xcd_bounds = nullptr;  // [5 lane counts][9] dense group bounds per XCD (device)
   int64_t* step_wl = nullptr;     // [wl_capacity]
   int32_t* step_count = nullptr;  // [2]
   float* step_alpha = nullptr;    // [npix]
@@ -79,6 +80,7 @@ int launch_plan_regress(esim_plan pl, int32_t t, const int64_t* worklist, const 
   a.resid = resid;
   a.kappa = kappa;
   a.update_state = update_state ? 1 : 0;
+  a.xcd_bounds = (!worklist && pl->nclips > 1) ? pl->xcd_bounds + 9 * esim::lanes_index(L) : nullptr;
   int max_r = 0;
   for (const auto& c : pl->host) max_r = std::max(max_r, static_cast<int>(c.r));
   return hip_check(esim::launch_regress(a, pl->F, pl->f16, pl->host[0].precision, L, pl->blocks_per_cu,
@@ -232,8 +234,10 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     off = align(off + clip_bytes);
     const size_t o_bcount = off;
     off = align(off + sizeof(int32_t) * blk);
-    const size_t o_boff = off;
-    off = align(off + sizeof(int64_t) * blk);
+    const size_t o_chunk = off;
+    off = align(off + sizeof(int64_t) * ((blk + esim::kChunkBlocks - 1) / esim::kChunkBlocks));
+    const size_t o_xcd = off;
+    off = align(off + sizeof(int64_t) * 5 * 9);
     const size_t o_flags = off;
     off = align(off + sizeof(uint64_t) * blk * esim::kWavesPerBlock);
     const size_t o_pol = off;
@@ -248,12 +252,46 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     char* m = static_cast<char*>(pl->ws_mem);
     pl->dev = reinterpret_cast<esim::ClipDev*>(m + o_clips);
     pl->ws.bcount = reinterpret_cast<int32_t*>(m + o_bcount);
-    pl->ws.boffset = reinterpret_cast<int64_t*>(m + o_boff);
+    pl->ws.chunk = reinterpret_cast<int64_t*>(m + o_chunk);
+    pl->xcd_bounds = reinterpret_cast<int64_t*>(m + o_xcd);
     pl->ws.flags = reinterpret_cast<uint64_t*>(m + o_flags);
     pl->ws.pol = reinterpret_cast<uint64_t*>(m + o_pol);
     pl->ws.misc = reinterpret_cast<int64_t*>(m + o_misc);
+    // Dense launches of a multi-clip plan split the groups between the 8 XCDs
+    // by work (window size x groups per clip) rather than by count, since a
+    // clip's items cost in proportion to its window.
+    int64_t xb[5][9];
+    for (int q = 0; q < 5; ++q) {
+      double total = 0.0;
+      std::vector<double> wc(nclips);
+      std::vector<int64_t> gc(nclips);
+      for (int c = 0; c < nclips; ++c) {
+        const auto& cd = pl->host[c];
+        gc[c] = (c + 1 < nclips ? pl->host[c + 1].grp_off[q] : grp[q]) - cd.grp_off[q];
+        wc[c] = static_cast<double>(2 * cd.r + 1) * (2 * cd.r + 1) * (2 * cd.tr + 1);
+        total += wc[c] * static_cast<double>(gc[c]);
+      }
+      xb[q][0] = 0;
+      xb[q][8] = grp[q];
+      for (int x = 1; x < 8; ++x) {
+        const double target = total * x / 8.0;
+        double cum = 0.0;
+        int64_t idx = grp[q];
+        for (int c = 0; c < nclips; ++c) {
+          const double cw = wc[c] * static_cast<double>(gc[c]);
+          if (cum + cw >= target) {
+            idx = pl->host[c].grp_off[q] +
+                  std::min<int64_t>(gc[c], static_cast<int64_t>(std::ceil((target - cum) / wc[c])));
+            break;
+          }
+          cum += cw;
+        }
+        xb[q][x] = std::max(xb[q][x - 1], idx);
+      }
+    }
     e = hipMemcpy(pl->dev, pl->host.data(), clip_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(m + o_bcount, 0, off - o_bcount);
+    if (e == hipSuccess) e = hipMemcpy(pl->xcd_bounds, xb, sizeof xb, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       hipFree(pl->ws_mem);

@@ -20,8 +20,9 @@ struct EventsDev {
 
 hipError_t launch_log(const float* E, float* y, int64_t n, float eps, hipStream_t s);
 
-// Grids of at most this many blocks skip the scan kernel: each scatter block
-// sums the counts before it (at most 16 KiB of reads).
+// Grids of at most this many blocks skip the chunk kernel: each scatter block
+// sums the counts before it (at most 16 KiB of reads); larger grids sum chunk
+// totals and the counts inside their chunk.
 constexpr int64_t kDirectPrefixBlocks = 4096;
 
 // flag -> (scan) -> scatter.  mode kFlagThreshold writes the work list and

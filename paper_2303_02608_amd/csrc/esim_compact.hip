@@ -10,11 +10,12 @@
 //                        raw        - eq. 1 on y against L_ref;
 //                      wave ballots of the flags and polarities, block counts;
 //                      block 0 records the event base.
-//   scan_kernel        one block: exclusive scan of the block counts (only for
+//   chunk_kernel       totals of chunks of kChunkBlocks block counts (only for
 //                      grids above kDirectPrefixBlocks blocks).
-//   scatter_kernel     each block's offset: the scan's, or the sum of the
-//                      counts of the blocks before it (read directly, no
-//                      inter-block signalling); rank = offset + popcounts of
+//   scatter_kernel     each block's offset: the sum of the counts of the
+//                      blocks before it, read directly (or as chunk totals plus
+//                      the counts inside its chunk), with no inter-block
+//                      signalling; rank = offset + popcounts of
 //                      the ballots below the lane; writes the work list
 //                      (threshold) and/or the events; the last block writes
 //                      the count and advances the event count.
@@ -41,37 +42,6 @@ __global__ void __launch_bounds__(256) log_kernel(const float* __restrict__ E, f
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
     y[i] = logf(E[i] + eps);
-}
-
-// Exclusive scan of one value per thread of the block (blockDim.x a multiple
-// of the wave size, at most 1024); returns this thread's exclusive prefix and
-// the block total in *total.
-__device__ int64_t block_scan(int64_t v, int64_t* sh, int64_t* total) {
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-  int64_t x = v;
-#pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const int64_t y = __shfl_up(x, o);
-    if (lane >= o) x += y;
-  }
-  if (lane == kWave - 1) sh[w] = x;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int64_t run = 0;
-    for (int k = 0; k < nw; ++k) {
-      const int64_t s = sh[k];
-      sh[k] = run;
-      run += s;
-    }
-    sh[16] = run;
-  }
-  __syncthreads();
-  const int64_t ex = sh[w] + x - v;
-  *total = sh[16];
-  __syncthreads();
-  return ex;
 }
 
 __global__ void __launch_bounds__(kBlock)
@@ -133,30 +103,15 @@ flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, floa
   }
 }
 
-// One block: exclusive scan of the block counts into ws.boffset.
-__global__ void __launch_bounds__(1024) scan_kernel(Workspace ws, int64_t nblk) {
-  __shared__ int64_t sh[17];
-  const int64_t nt = blockDim.x;
-  const int64_t chunk = (nblk + nt - 1) / nt;
-  const int64_t lo = min(nblk, chunk * threadIdx.x);
-  const int64_t hi = min(nblk, chunk * (threadIdx.x + 1));
-  int64_t s = 0;
-  for (int64_t b = lo; b < hi; ++b) s += ws.bcount[b];
-  int64_t tot;
-  int64_t off = block_scan(s, sh, &tot);
-  for (int64_t b = lo; b < hi; ++b) {
-    ws.boffset[b] = off;
-    off += ws.bcount[b];
-  }
-}
-
-// Sum of the counts of blocks [0, b), by one block.
-__device__ int64_t counts_before(const Workspace& ws, int64_t b) {
+// Sum of a[lo, hi) by one block of kBlock threads.
+template <class V>
+__device__ int64_t block_sum(const V* __restrict__ a, int64_t lo, int64_t hi) {
   __shared__ int64_t red[kWavesPerBlock];
   int64_t s = 0;
-  for (int64_t k = threadIdx.x; k < b; k += blockDim.x) s += ws.bcount[k];
+  for (int64_t k = lo + threadIdx.x; k < hi; k += blockDim.x) s += a[k];
 #pragma unroll
   for (int o = kWave / 2; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  __syncthreads();
   if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
   __syncthreads();
   int64_t tot = 0;
@@ -165,11 +120,27 @@ __device__ int64_t counts_before(const Workspace& ws, int64_t b) {
   return tot;
 }
 
+// Counts of blocks [0, b): directly, or (chunked) the chunk totals before b's
+// chunk plus the counts inside it.
+__device__ int64_t counts_before(const Workspace& ws, int64_t b, bool chunked) {
+  if (!chunked) return block_sum(ws.bcount, 0, b);
+  const int64_t c = b / kChunkBlocks;
+  const int64_t s = block_sum(ws.chunk, 0, c);
+  return s + block_sum(ws.bcount, c * kChunkBlocks, b);
+}
+
+// Block c: the total count of blocks [c * kChunkBlocks, (c + 1) * kChunkBlocks).
+__global__ void __launch_bounds__(kBlock) chunk_kernel(Workspace ws, int64_t nblk) {
+  const int64_t c = blockIdx.x;
+  const int64_t t = block_sum(ws.bcount, c * kChunkBlocks, min(nblk, (c + 1) * kChunkBlocks));
+  if (threadIdx.x == 0) ws.chunk[c] = t;
+}
+
 __global__ void __launch_bounds__(kBlock)
-scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, Workspace ws, int direct,
+scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, Workspace ws, int chunked,
                int64_t* __restrict__ worklist, int32_t* __restrict__ count, EventsDev ev) {
   const int64_t b = blockIdx.x;
-  const int64_t off0 = direct ? counts_before(ws, b) : ws.boffset[b];
+  const int64_t off0 = counts_before(ws, b, chunked != 0);
   const int64_t base = ws.misc[0];
   if (b == gridDim.x - 1 && threadIdx.x == 0) {
     const int64_t total = off0 + ws.bcount[b];
@@ -295,11 +266,13 @@ hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, i
   int64_t* wl = mode == kFlagThreshold ? worklist : nullptr;
   hipLaunchKernelGGL(flag_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
                      t, mode, dl, alpha, ws, ev ? ev->count : nullptr);
-  const int direct = nblk <= kDirectPrefixBlocks ? 1 : 0;
-  if (!direct) hipLaunchKernelGGL(scan_kernel, dim3(1), dim3(1024), 0, s, ws, nblk);
+  const int chunked = nblk > kDirectPrefixBlocks ? 1 : 0;
+  if (chunked)
+    hipLaunchKernelGGL(chunk_kernel, dim3(static_cast<unsigned>((nblk + kChunkBlocks - 1) / kChunkBlocks)),
+                       dim3(kBlock), 0, s, ws, nblk);
   EventsDev none{};
   hipLaunchKernelGGL(scatter_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
-                     t, mode, ws, direct, wl, wl ? count : nullptr, ev ? *ev : none);
+                     t, mode, ws, chunked, wl, wl ? count : nullptr, ev ? *ev : none);
   return hipGetLastError();
 }
 

@@ -38,11 +38,13 @@ struct ClipDev {
 // Compaction workspace of a plan (device).
 struct Workspace {
   int32_t* bcount;         // [nblk] flagged pixels per block
-  int64_t* boffset;        // [nblk] output offset of each block
   uint64_t* flags;         // [nblk][kWavesPerBlock] flag ballots
   uint64_t* pol;           // [nblk][kWavesPerBlock] positive-polarity ballots
   int64_t* misc;           // [4] [0] event base of the current step
+  int64_t* chunk;          // [ceil(nblk / kChunkBlocks)] counts per chunk of blocks
 };
+
+constexpr int64_t kChunkBlocks = 1024;     // blocks per chunk of the two-level prefix
 
 // Stored feature value f of pixel p at frame t (FP16 storage converted).
 __device__ __forceinline__ float feat_value(const ClipDev& C, int t, int f, int64_t p) {
@@ -141,6 +143,7 @@ struct RegressArgs {
   float* resid;
   float* kappa;
   int32_t update_state;     // write each item's model into its clip state (Sec. 2.2)
+  const int64_t* xcd_bounds;  // dense multi-clip launches: [9] group bounds per XCD (device)
 };
 
 // Regression launcher: picks the kernel instance for (F, dtype, precision)

@@ -455,15 +455,25 @@ __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j
 // same L2; otherwise a plain grid stride is used.
 struct GroupIter {
   int64_t g, end, step;
-  __device__ __forceinline__ GroupIter(int64_t ngroups) {
+  // xb (nullable): the groups of XCD x are [xb[x], xb[x + 1]) (a split by
+  // work rather than by count); otherwise XCD x takes the x-th eighth.
+  __device__ __forceinline__ GroupIter(int64_t ngroups, const int64_t* xb = nullptr) {
     const int64_t nblk = gridDim.x;
     const int64_t wib = threadIdx.x / kWave;            // wave in block
     const int64_t wpb = blockDim.x / kWave;
     if (nblk >= 8 && nblk % 8 == 0) {
       const int64_t x = blockIdx.x % 8;
-      const int64_t chunk = (ngroups + 7) / 8;
-      g = x * chunk + (blockIdx.x / 8) * wpb + wib;
-      end = min(ngroups, (x + 1) * chunk);
+      int64_t lo, hi;
+      if (xb) {
+        lo = xb[x];
+        hi = min(ngroups, xb[x + 1]);
+      } else {
+        const int64_t chunk = (ngroups + 7) / 8;
+        lo = x * chunk;
+        hi = min(ngroups, (x + 1) * chunk);
+      }
+      g = lo + (blockIdx.x / 8) * wpb + wib;
+      end = hi;
       step = (nblk / 8) * wpb;
     } else {
       g = static_cast<int64_t>(blockIdx.x) * wpb + wib;
