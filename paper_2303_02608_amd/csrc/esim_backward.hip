@@ -17,13 +17,15 @@
 //                         and sums the bandwidth gradient over the item's lanes
 //   gather_kernel         per input (frame, pixel): sums, in a fixed order, the
 //                         contributions of every item whose window holds it
+//                         (item rows staged in LDS per tile of an input row)
 //   reduce_gb_*           fixed-order two-level sum of the per-item b gradients
 #include "esim_wlr.h"
 
 namespace esim {
 namespace {
 
-constexpr int kAdjLanes = 4;
+constexpr int kAdjLanes = 4;        // lanes per item, windows wider than 16 columns
+constexpr int kAdjLanesWide = 16;   // lanes per item, windows of at most 16 columns
 constexpr int kRedBlocks = 256;
 
 struct BwdDev {
@@ -61,7 +63,7 @@ map_items_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ 
 }
 
 template <int F, int L, bool F16>
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F <= 8 ? 2 : 1)))
 adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ items,
                const float* __restrict__ g_alpha, BwdDev bd) {
   constexpr int D = F + 2;
@@ -90,13 +92,13 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
     make_geom(geo, C, active ? pix : 0, active ? t : 0, 0, C.T, active);
 
     Gram<F, double> gm;
-    gm.zero();
+    gm.zero_snap();
     window_loop<F, L, F16, double>(
-        geo, j, [&](double) { gm.pass_begin(); },
+        geo, j, [&](double) { gm.pass_begin_snap(); },
         [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-          gm.add(w, yd, v, vy);
+          gm.add_onepass(w, yd, v, vy);
         },
-        [&](double vx) { gm.pass_end(vx); });
+        [&](double vx) { gm.pass_end_snap(vx); });
     gm.template lane_sum<L>();
     double M[P * (P + 1) / 2], rhs[P], th[P], anorm;
     const double iW = gram_solve<F, double>(gm, C, M, rhs, th, anorm);
@@ -145,32 +147,60 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
   }
 }
 
-__global__ void __launch_bounds__(256)
+// One block per (frame, row, tile of kGatherTile columns) of inputs.  For each
+// item row (tc, yc) that can reach the tile, in ascending order, the block
+// stages the map row and the items' contributions to this input row (2r + 1
+// consecutive slots per item, coalesced) in LDS; each thread then adds, for
+// its input column, the items at xc = xq - r .. xq + r in ascending order.
+// The order of the sum (tc, yc, xc ascending) is fixed, so the result does not
+// depend on scheduling.
+constexpr int kGatherTile = 256;
+
+__global__ void __launch_bounds__(kGatherTile)
 gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ g_y) {
+  extern __shared__ float sm[];
   const ClipDev& C = clips[0];
   const int r = C.r, tr = C.tr, W = C.W, H = C.H, T = C.T;
   const int span = 2 * r + 1;
-  const int64_t N = static_cast<int64_t>(T) * C.HW;
-  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
-  for (int64_t q = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; q < N; q += stride) {
-    const int tq = static_cast<int>(q / C.HW);
-    const int64_t p = q - static_cast<int64_t>(tq) * C.HW;
-    const int yq = static_cast<int>(p / W), xq = static_cast<int>(p - static_cast<int64_t>(yq) * W);
-    double acc = 0.0;
-    const int t0 = max(0, tq - tr), t1 = min(T - 1, tq + tr);
-    const int y0 = max(0, yq - r), y1 = min(H - 1, yq + r);
-    const int x0 = max(0, xq - r), x1 = min(W - 1, xq + r);
-    for (int tc = t0; tc <= t1; ++tc)
-      for (int yc = y0; yc <= y1; ++yc) {
-        const int32_t* row = bd.item_map + static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W;
-        const int base = ((tq - tc + tr) * span + (yq - yc + r)) * span + xq + r;
-        for (int xc = x0; xc <= x1; ++xc) {
-          const int32_t it = row[xc];
-          if (it >= 0) acc += static_cast<double>(bd.contrib[static_cast<int64_t>(it) * bd.S + (base - xc)]);
+  const int seg = kGatherTile + 2 * r;                 // staged columns
+  int32_t* mrow = reinterpret_cast<int32_t*>(sm);      // [seg]
+  float* cx = sm + seg;                                // [seg][span]
+  const int ntile = (W + kGatherTile - 1) / kGatherTile;
+  const int64_t b = blockIdx.x;
+  const int tile = static_cast<int>(b % ntile);
+  const int64_t rowq = b / ntile;                      // tq * H + yq
+  const int tq = static_cast<int>(rowq / H), yq = static_cast<int>(rowq % H);
+  const int x_lo = tile * kGatherTile;
+  const int xs = x_lo - r;                             // column of staged index 0
+  const int xq = x_lo + static_cast<int>(threadIdx.x);
+  double acc = 0.0;
+  const int t0 = max(0, tq - tr), t1 = min(T - 1, tq + tr);
+  const int y0 = max(0, yq - r), y1 = min(H - 1, yq + r);
+  for (int tc = t0; tc <= t1; ++tc)
+    for (int yc = y0; yc <= y1; ++yc) {
+      const int32_t* row = bd.item_map + static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W;
+      for (int k = threadIdx.x; k < seg; k += kGatherTile) {
+        const int x = xs + k;
+        mrow[k] = (x >= 0 && x < W) ? row[x] : -1;
+      }
+      __syncthreads();
+      const int64_t sbase = static_cast<int64_t>((tq - tc + tr) * span + (yq - yc + r)) * span;
+      for (int k = threadIdx.x; k < seg * span; k += kGatherTile) {
+        const int c = k / span, m = k - c * span;
+        const int32_t it = mrow[c];
+        if (it >= 0) cx[c * span + m] = bd.contrib[static_cast<int64_t>(it) * bd.S + sbase + m];
+      }
+      __syncthreads();
+      if (xq < W) {
+        // items at xc = xq - r + m (staged index threadIdx.x + m), slot x-index span - 1 - m
+        for (int m = 0; m < span; ++m) {
+          const int c = static_cast<int>(threadIdx.x) + m;
+          if (mrow[c] >= 0) acc += static_cast<double>(cx[c * span + (span - 1 - m)]);
         }
       }
-    if (acc != 0.0) g_y[q] += static_cast<float>(acc);
-  }
+      __syncthreads();
+    }
+  if (xq < W && acc != 0.0) g_y[rowq * W + xq] += static_cast<float>(acc);
 }
 
 template <int D>
@@ -206,24 +236,25 @@ __global__ void reduce_gb_final(BwdDev bd, int nblk, int D, double* g_b) {
 using AdjFn = void (*)(const ClipDev*, const int64_t*, const float*, BwdDev);
 
 template <int F>
-AdjFn pick_adj(bool f16) {
+AdjFn pick_adj(bool f16, bool wide) {
+  if (wide) return f16 ? adjoint_kernel<F, kAdjLanesWide, true> : adjoint_kernel<F, kAdjLanesWide, false>;
   return f16 ? adjoint_kernel<F, kAdjLanes, true> : adjoint_kernel<F, kAdjLanes, false>;
 }
 
-AdjFn pick(int F, bool f16) {
+AdjFn pick(int F, bool f16, bool wide) {
   switch (F) {
-    case 1: return pick_adj<1>(f16);
-    case 2: return pick_adj<2>(f16);
-    case 3: return pick_adj<3>(f16);
-    case 4: return pick_adj<4>(f16);
-    case 5: return pick_adj<5>(f16);
-    case 6: return pick_adj<6>(f16);
-    case 7: return pick_adj<7>(f16);
-    case 8: return pick_adj<8>(f16);
-    case 9: return pick_adj<9>(f16);
-    case 10: return pick_adj<10>(f16);
-    case 11: return pick_adj<11>(f16);
-    case 12: return pick_adj<12>(f16);
+    case 1: return pick_adj<1>(f16, wide);
+    case 2: return pick_adj<2>(f16, wide);
+    case 3: return pick_adj<3>(f16, wide);
+    case 4: return pick_adj<4>(f16, wide);
+    case 5: return pick_adj<5>(f16, wide);
+    case 6: return pick_adj<6>(f16, wide);
+    case 7: return pick_adj<7>(f16, wide);
+    case 8: return pick_adj<8>(f16, wide);
+    case 9: return pick_adj<9>(f16, wide);
+    case 10: return pick_adj<10>(f16, wide);
+    case 11: return pick_adj<11>(f16, wide);
+    case 12: return pick_adj<12>(f16, wide);
     default: return nullptr;
   }
 }
@@ -287,7 +318,11 @@ size_t backward_scratch_bytes(const ClipDev& hc, int64_t n) { return layout(hc, 
 hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   const ClipDev& hc = *a.host_clip;
   const int F = hc.F, D = F + 2;
-  AdjFn adj = pick(F, hc.feat_f16 != 0);
+  // 16 lanes per item (one column each) when the window has at most 16
+  // columns: an item's contributions to a window row are then one coalesced
+  // 4(2r+1)-byte store
+  const bool wide = 2 * hc.r + 1 <= kAdjLanesWide;
+  AdjFn adj = pick(F, hc.feat_f16 != 0, wide);
   RedFn rb = pick_red(D);
   if (!adj || !rb) return hipErrorInvalidValue;
   const Layout l = layout(hc, a.n);
@@ -298,12 +333,18 @@ hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(fill_map_kernel, dim3(grid_for(map_n, 4096)), dim3(256), 0, s, bd.item_map, map_n);
   hipLaunchKernelGGL(map_items_kernel, dim3(grid_for(a.n, 4096)), dim3(256), 0, s, a.clip, a.items, a.n,
                      a.g_alpha, bd.item_map);
-  const int G = kWave / kAdjLanes;
+  const int L = wide ? kAdjLanesWide : kAdjLanes;
+  const int G = kWave / L;
   int64_t blocks = ((a.n + G - 1) / G + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (blocks > 1024) blocks = 1024;
+  if (blocks > 2048) blocks = 2048;
   blocks = (blocks + 7) / 8 * 8;   // a multiple of the 8 XCDs (see GroupIter)
   hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a.clip, a.items, a.g_alpha, bd);
-  hipLaunchKernelGGL(gather_kernel, dim3(grid_for(map_n, 8192)), dim3(256), 0, s, a.clip, bd, a.g_y);
+  const int span = 2 * hc.r + 1;
+  const int seg = kGatherTile + 2 * hc.r;
+  const size_t lds = sizeof(float) * static_cast<size_t>(seg) * (span + 1);
+  const int64_t gblocks = static_cast<int64_t>(hc.T) * hc.H * ((hc.W + kGatherTile - 1) / kGatherTile);
+  hipLaunchKernelGGL(gather_kernel, dim3(static_cast<unsigned>(gblocks)), dim3(kGatherTile), lds, s, a.clip, bd,
+                     a.g_y);
   hipLaunchKernelGGL(rb, dim3(kRedBlocks), dim3(256), 0, s, bd);
   hipLaunchKernelGGL(reduce_gb_final, dim3(1), dim3(64), 0, s, bd, kRedBlocks, D, a.g_b);
   return hipGetLastError();
