@@ -245,7 +245,7 @@ int esim_step(esim_plan plan, int32_t t, int32_t mode, float* dl, esim_events_bu
  *   g_b[j]            += sum_items g_alpha sum_i (s_i r_i - lambda v^T E theta)
  *                        / W * w_i u_ij^2 / (h^2 b_j^3),  j < F + 2.
  * The window is recomputed, not stored.  Single-clip plans only; the clip's
- * features must stay below 4 GiB.  scratch: esim_backward_scratch_bytes.
+ * features must stay below 4 GiB and r <= 25.  scratch: esim_backward_scratch_bytes.
  * Errors: E_INVAL, E_CAPACITY (scratch too small), E_UNSUPPORTED. */
 size_t esim_backward_scratch_bytes(esim_plan plan, int64_t n);
 int esim_wlr_backward(esim_plan plan, const int64_t* items, int64_t n, const float* g_alpha,

@@ -488,6 +488,8 @@ int esim_wlr_backward(esim_plan pl, const int64_t* items, int64_t n, const float
     if (!items || !g_alpha || !g_y || !g_b) return fail(ESIM_E_INVAL, "null argument");
     if (pl->max_feat_bytes >= (1ull << 32))
       return fail(ESIM_E_UNSUPPORTED, "backward needs a feature array below 4 GiB");
+    if (esim::backward_gather_lds_bytes(pl->host[0]) > esim::kMaxGatherLds)
+      return fail(ESIM_E_UNSUPPORTED, "backward supports window radii up to 25");
     const size_t need = esim::backward_scratch_bytes(pl->host[0], n);
     if (!scratch || scratch_bytes < need) return fail(ESIM_E_CAPACITY, "scratch too small");
     esim::BackwardArgs a{pl->dev, &pl->host[0], items, n, g_alpha, g_y, g_b, scratch, scratch_bytes};

@@ -173,6 +173,8 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   const int x_lo = tile * kGatherTile;
   const int xs = x_lo - r;                             // column of staged index 0
   const int xq = x_lo + static_cast<int>(threadIdx.x);
+  const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
+  const int wave = static_cast<int>(threadIdx.x) / kWave;
   double acc = 0.0;
   const int t0 = max(0, tq - tr), t1 = min(T - 1, tq + tr);
   const int y0 = max(0, yq - r), y1 = min(H - 1, yq + r);
@@ -184,11 +186,21 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
         mrow[k] = (x >= 0 && x < W) ? row[x] : -1;
       }
       __syncthreads();
+      // each wave walks the present items of its 64-column chunks (a
+      // wave-uniform loop over the ballot); lanes m < span load the item's
+      // slots m, one coalesced 4 (2r + 1)-byte read per item
       const int64_t sbase = static_cast<int64_t>((tq - tc + tr) * span + (yq - yc + r)) * span;
-      for (int k = threadIdx.x; k < seg * span; k += kGatherTile) {
-        const int c = k / span, m = k - c * span;
-        const int32_t it = mrow[c];
-        if (it >= 0) cx[c * span + m] = bd.contrib[static_cast<int64_t>(it) * bd.S + sbase + m];
+      for (int base = wave * kWave; base < seg; base += kGatherTile) {
+        const int c = base + lane;
+        const int32_t it = c < seg ? mrow[c] : -1;
+        uint64_t mask = __ballot(it >= 0);
+        while (mask != 0) {
+          const int bit = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+          mask &= mask - 1;
+          const int32_t itc = __shfl(it, bit);
+          for (int m = lane; m < span; m += kWave)
+            cx[(base + bit) * span + m] = bd.contrib[static_cast<int64_t>(itc) * bd.S + sbase + m];
+        }
       }
       __syncthreads();
       if (xq < W) {
@@ -315,6 +327,10 @@ unsigned grid_for(int64_t n, int64_t cap) {
 
 size_t backward_scratch_bytes(const ClipDev& hc, int64_t n) { return layout(hc, n).total; }
 
+size_t backward_gather_lds_bytes(const ClipDev& hc) {
+  return sizeof(float) * static_cast<size_t>(kGatherTile + 2 * hc.r) * (2 * hc.r + 2);
+}
+
 hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   const ClipDev& hc = *a.host_clip;
   const int F = hc.F, D = F + 2;
@@ -339,9 +355,7 @@ hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   if (blocks > 2048) blocks = 2048;
   blocks = (blocks + 7) / 8 * 8;   // a multiple of the 8 XCDs (see GroupIter)
   hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a.clip, a.items, a.g_alpha, bd);
-  const int span = 2 * hc.r + 1;
-  const int seg = kGatherTile + 2 * hc.r;
-  const size_t lds = sizeof(float) * static_cast<size_t>(seg) * (span + 1);
+  const size_t lds = backward_gather_lds_bytes(hc);
   const int64_t gblocks = static_cast<int64_t>(hc.T) * hc.H * ((hc.W + kGatherTile - 1) / kGatherTile);
   hipLaunchKernelGGL(gather_kernel, dim3(static_cast<unsigned>(gblocks)), dim3(kGatherTile), lds, s, a.clip, bd,
                      a.g_y);

@@ -175,6 +175,9 @@ struct BackwardArgs {
   size_t scratch_bytes;
 };
 size_t backward_scratch_bytes(const ClipDev& hc, int64_t n);
+// LDS of the gather kernel (a staged input-row tile); at most 64 KiB is used.
+size_t backward_gather_lds_bytes(const ClipDev& hc);
+constexpr size_t kMaxGatherLds = 65536;
 hipError_t launch_backward(const BackwardArgs& a, hipStream_t s);
 
 }  // namespace esim
