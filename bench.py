@@ -19,7 +19,9 @@ regression and a 24-frame thresholded conversion with the FP64 Gram and with
 the compensated-FP32 Gram), `batch` (the 32-clip batch, frames scaled down to
 about 2e8 pixel-frames: one batched plan against the clips converted one by
 one) and `diff` (640x480x60: forward regressions of the differentiation loss
-and their adjoint).
+and their adjoint), `quality` (events of the three conversions against ESIM on
+the noise-free frames: precision, recall, F1 and Chamfer distance over a sweep
+of C, with the conversion times).
 
 Roofline: the dominant kernel is the regression.  Its launches are bracketed
 with HIP events on the launch stream during an instrumented eager pass of the
@@ -243,6 +245,46 @@ def workload_diff(args, B, synth, Simulator):
             "adjoint_flop_model": "forward F_reg + 60 FLOP per window sample"}
 
 
+def workload_quality(args, B, synth, Simulator):
+    """Event quality against ESIM on the noise-free frames of the DVS clip
+    (Sec. 3 "Quantitative comparison", Tables 1 and A2 on synthetic scenes),
+    with conversion times, over a sweep of C."""
+    import torch
+    from paper_2303_02608_amd import quality as Q
+    cfg = synth.config_spec(1)
+    spec = cfg["spec"]
+    t0 = time.time()
+    d = synth.make_clip(spec, device="cuda", reference=True)
+    y = B.log_brightness(d["E"])
+    y_ref = B.log_brightness(d["E_ref"])
+    feat = d["feat"]
+    torch.cuda.synchronize()
+    log(f"generated {spec.W}x{spec.H}x{spec.T} with reference frames in {time.time() - t0:.1f}s")
+    T, F, H, W = feat.shape
+    taus, rmax = [5e-4, 2e-3, 5e-3, 1e-2], 0.05
+    rows = []
+    for C in (0.15, 0.25, 0.5, 0.75, 1.0):
+        p = B.Params(r=cfg["r"], tr=cfg["tr"], C=C)
+        ref = Simulator(y_ref, feat, p).run("raw")
+        refd = Q.to_device(ref)
+        row = {"C": C, "reference_events": ref["count"]}
+        for mode in ("raw", "exhaustive", "thresholded"):
+            sim = Simulator(y, feat, p)
+            run = _graph(lambda s=sim, m=mode: s.enqueue(m))
+            ms = _time_ms(run, 2)
+            ev = sim.events()
+            m = Q.metrics(Q.to_device(ev), refd, W, H, T, taus, rmax)
+            row[mode] = {"ms": round(ms, 3), "events": ev["count"],
+                         "P": [round(v, 4) for v in m["P"]], "R": [round(v, 4) for v in m["R"]],
+                         "F": [round(v, 4) for v in m["F"]], "CD": m["CD"]}
+            del sim, run
+            log(f"C={C} {mode}: {ms:.2f} ms, {ev['count']} events, F {row[mode]['F']}")
+        rows.append(row)
+    return {"workload": f"quality DVS {W}x{H}x{T}, r={cfg['r']}, tr={cfg['tr']}; reference = ESIM on the "
+                        f"noise-free frames; coordinates normalised by (W, H, T)",
+            "taus": taus, "rmax": rmax, "sweep": rows}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -260,7 +302,7 @@ def main():
                     help="load the clip saved by --save-clip instead of generating it")
     ap.add_argument("--schedule", type=str, default=None,
                     help="lanes_dense,lanes_list,blocks_per_cu (skips the autotuner)")
-    ap.add_argument("--workload", choices=("dvs", "precision", "batch", "diff"), default="dvs",
+    ap.add_argument("--workload", choices=("dvs", "precision", "batch", "diff", "quality"), default="dvs",
                     help="dvs (default, the contract line) or one of the extension workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (the "
@@ -286,7 +328,8 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     if args.workload != "dvs":
-        fn = {"precision": workload_precision, "batch": workload_batch, "diff": workload_diff}
+        fn = {"precision": workload_precision, "batch": workload_batch, "diff": workload_diff,
+              "quality": workload_quality}
         res = fn[args.workload](args, B, synth, Simulator)
         res = {"metric": f"{args.workload} workload", "n_gpus": 1, "dtype": "f64",
                "data": "synthetic", **res}

@@ -251,6 +251,29 @@ size_t esim_backward_scratch_bytes(esim_plan plan, int64_t n);
 int esim_wlr_backward(esim_plan plan, const int64_t* items, int64_t n, const float* g_alpha,
                       float* g_y, double* g_b, void* scratch, size_t scratch_bytes, void* stream);
 
+/* ---- event-set comparison ------------------------------------------------ */
+
+/* Nearest same-polarity neighbour distances (Sec. 3, "Quantitative comparison":
+ * events are signed points (x, y, t); precision and recall count the events of
+ * one set whose closest event of the same polarity in the other set lies
+ * within a distance threshold).  For each of the nq query events, d[i] is the
+ * Euclidean distance, in the scaled coordinates (x scale_x, y scale_y,
+ * t scale_t), to the nearest of the ns source events with the same polarity
+ * (p = +1 or -1), or +inf when none lies within rmax.  The search is exact
+ * within rmax.  Events outside [0, W) x [0, H) x [0, T) or with another p are
+ * ignored as sources and get +inf as queries.  All arrays are device memory;
+ * d is FP64.  scratch: esim_nn_scratch_bytes(W, H, T) bytes of device memory
+ * (occupancy bitmaps, overwritten).  The x extent of rmax, rmax / scale_x, must
+ * stay below 4096 columns.
+ * Errors: E_INVAL (shapes, scales, null pointers), E_CAPACITY (scratch too
+ * small), E_UNSUPPORTED (radius too wide). */
+size_t esim_nn_scratch_bytes(int32_t W, int32_t H, int32_t T);
+int esim_nn_distances(const int32_t* src_x, const int32_t* src_y, const int32_t* src_t,
+                      const int8_t* src_p, int64_t ns, const int32_t* qry_x, const int32_t* qry_y,
+                      const int32_t* qry_t, const int8_t* qry_p, int64_t nq, int32_t W, int32_t H,
+                      int32_t T, double scale_x, double scale_y, double scale_t, double rmax, double* d,
+                      void* scratch, size_t scratch_bytes, void* stream);
+
 /* ---- diagnostics ------------------------------------------------------- */
 const char* esim_status_string(int status);
 /* Message of the last failed call on this thread ("" if none). */

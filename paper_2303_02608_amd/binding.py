@@ -72,6 +72,10 @@ SIGNATURES = {
     "esim_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "esim_backward_scratch_bytes": (_sz, [_vp, _i64]),
     "esim_wlr_backward": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "esim_nn_scratch_bytes": (_sz, [_i32, _i32, _i32]),
+    "esim_nn_distances": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32,
+                                 ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                 _vp, _vp, _sz, _vp]),
     "esim_status_string": (ctypes.c_char_p, [_i32]),
     "esim_last_error": (ctypes.c_char_p, []),
     "esim_build_info": (ctypes.c_char_p, []),
@@ -263,6 +267,26 @@ def step(plan: Plan, t: int, mode: int, ev: Optional[Events] = None, dl=None, st
     evs = ev.struct() if ev is not None else None
     _check(load().esim_step(plan.h, t, mode, _ptr(dl), ctypes.byref(evs) if evs is not None else None,
                             _stream(stream)), "step")
+
+
+def nn_distances(src: dict, qry: dict, W: int, H: int, T: int, rmax: float, scales=None,
+                 scratch: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """Distance from every query event to the nearest source event of the same
+    polarity (esim_nn_distances); src/qry: dicts of device tensors x, y, t
+    (int32) and p (int8).  Scales default to 1/W, 1/H, 1/T."""
+    sx, sy, st = scales if scales is not None else (1.0 / W, 1.0 / H, 1.0 / T)
+    nq = int(qry["x"].numel())
+    dev = qry["x"].device
+    d = torch.empty(nq, dtype=torch.float64, device=dev)
+    need = int(load().esim_nn_scratch_bytes(W, H, T))
+    if scratch is None or scratch.numel() * scratch.element_size() < need:
+        scratch = torch.empty(need, dtype=torch.uint8, device=dev)
+    _check(load().esim_nn_distances(_ptr(src["x"]), _ptr(src["y"]), _ptr(src["t"]), _ptr(src["p"]),
+                                    int(src["x"].numel()), _ptr(qry["x"]), _ptr(qry["y"]), _ptr(qry["t"]),
+                                    _ptr(qry["p"]), nq, W, H, T, sx, sy, st, float(rmax), _ptr(d),
+                                    _ptr(scratch), scratch.numel() * scratch.element_size(),
+                                    _stream(stream)), "nn_distances")
+    return d
 
 
 def backward_scratch_bytes(plan: Plan, n: int) -> int:

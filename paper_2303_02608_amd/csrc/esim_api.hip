@@ -499,6 +499,54 @@ int esim_wlr_backward(esim_plan pl, const int64_t* items, int64_t n, const float
   }
 }
 
+size_t esim_nn_scratch_bytes(int32_t W, int32_t H, int32_t T) {
+  if (W < 1 || H < 1 || T < 1) return 0;
+  return esim::nn_scratch_bytes(W, H, T);
+}
+
+int esim_nn_distances(const int32_t* src_x, const int32_t* src_y, const int32_t* src_t, const int8_t* src_p,
+                      int64_t ns, const int32_t* qry_x, const int32_t* qry_y, const int32_t* qry_t,
+                      const int8_t* qry_p, int64_t nq, int32_t W, int32_t H, int32_t T, double scale_x,
+                      double scale_y, double scale_t, double rmax, double* d, void* scratch,
+                      size_t scratch_bytes, void* stream) {
+  try {
+    if (W < 1 || H < 1 || T < 1 || ns < 0 || nq < 0) return fail(ESIM_E_INVAL, "bad shape or count");
+    if (!(scale_x > 0) || !(scale_y > 0) || !(scale_t > 0) || !(rmax >= 0) || std::isinf(rmax))
+      return fail(ESIM_E_INVAL, "scales must be positive and rmax finite and >= 0");
+    if ((ns > 0 && (!src_x || !src_y || !src_t || !src_p)) || (nq > 0 && (!qry_x || !qry_y || !qry_t || !qry_p || !d)))
+      return fail(ESIM_E_INVAL, "null event array");
+    if (!scratch || scratch_bytes < esim::nn_scratch_bytes(W, H, T)) return fail(ESIM_E_CAPACITY, "scratch too small");
+    const double ex = std::floor(rmax / scale_x), ey = std::floor(rmax / scale_y), et = std::floor(rmax / scale_t);
+    if (ex >= 4096) return fail(ESIM_E_UNSUPPORTED, "rmax spans 4096 columns or more");
+    esim::NnArgs a{};
+    a.sx = src_x;
+    a.sy = src_y;
+    a.st = src_t;
+    a.sp = src_p;
+    a.ns = ns;
+    a.qx = qry_x;
+    a.qy = qry_y;
+    a.qt = qry_t;
+    a.qp = qry_p;
+    a.nq = nq;
+    a.W = W;
+    a.H = H;
+    a.T = T;
+    a.scale_x = scale_x;
+    a.scale_y = scale_y;
+    a.scale_t = scale_t;
+    a.rmax = rmax;
+    a.rx = static_cast<int>(std::min<double>(ex, W));
+    a.ry = static_cast<int>(std::min<double>(ey, H));
+    a.rt = static_cast<int>(std::min<double>(et, T));
+    a.d = d;
+    a.scratch = scratch;
+    return hip_check(esim::launch_nn(a, static_cast<hipStream_t>(stream)), "nn_distances");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
 // Schedule override used by the autotuner: lanes per item for dense and for
 // work-list launches (1, 2, 4, 8, 16) and persistent blocks per CU.  Not part of
 // the hot path.

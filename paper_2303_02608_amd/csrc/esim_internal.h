@@ -180,4 +180,21 @@ size_t backward_gather_lds_bytes(const ClipDev& hc);
 constexpr size_t kMaxGatherLds = 65536;
 hipError_t launch_backward(const BackwardArgs& a, hipStream_t s);
 
+// Nearest same-polarity neighbour distances (event-set comparison).
+struct NnArgs {
+  const int32_t *sx, *sy, *st;  // source events
+  const int8_t* sp;
+  int64_t ns;
+  const int32_t *qx, *qy, *qt;  // query events
+  const int8_t* qp;
+  int64_t nq;
+  int W, H, T;
+  double scale_x, scale_y, scale_t, rmax;
+  int rx, ry, rt;               // lattice extents of rmax
+  double* d;
+  void* scratch;
+};
+size_t nn_scratch_bytes(int W, int H, int T);
+hipError_t launch_nn(const NnArgs& a, hipStream_t s);
+
 }  // namespace esim

@@ -338,13 +338,16 @@ def _channels(F: int) -> list:
 
 
 def make_clip(spec: ClipSpec, device="cpu", frames: Optional[Sequence[int]] = None,
-              crop: Optional[Sequence[int]] = None):
+              crop: Optional[Sequence[int]] = None, reference: bool = False):
     """Render a clip.  Returns a dict with ``E``, ``var`` ``[T][H][W]`` f32 and
     ``feat`` ``[T][F][H][W]`` (f32 or f16), all on ``device``.
 
     ``frames`` selects frames and ``crop = (x0, y0, w, h)`` a pixel window; the
     values are those of the full clip at the same positions (the randomness is
-    keyed by the full-frame pixel index)."""
+    keyed by the full-frame pixel index).  With ``reference`` the dict also
+    holds ``E_ref``: the same sub-pixel samples without the radiance noise
+    factor, i.e. the noise-free render the noisy one estimates (the stand-in
+    for the paper's high-spp reference frames)."""
     s = spec
     dev = torch.device(device)
     scene = _Scene(s, dev)
@@ -356,6 +359,7 @@ def make_clip(spec: ClipSpec, device="cpu", frames: Optional[Sequence[int]] = No
     assert 0 <= x0 and 0 <= y0 and x0 + cw <= s.W and y0 + ch <= s.H
     E = torch.empty((T, ch, cw), dtype=torch.float32, device=dev)
     V = torch.empty((T, ch, cw), dtype=torch.float32, device=dev)
+    E_ref = torch.empty((T, ch, cw), dtype=torch.float32, device=dev) if reference else None
     feat = torch.empty((T, s.F, ch, cw), dtype=fdt, device=dev)
     HW = ch * cw
     loc = torch.arange(HW, dtype=torch.int64, device=dev)
@@ -395,6 +399,8 @@ def make_clip(spec: ClipSpec, device="cpu", frames: Optional[Sequence[int]] = No
             Es = (a["E"] * X).reshape(nf, n, s.spp)
             m = Es.mean(dim=2)
             E[f0:f0 + nf].view(nf, HW)[:, c0:c1] = m
+            if reference:
+                E_ref[f0:f0 + nf].view(nf, HW)[:, c0:c1] = a["E"].reshape(nf, n, s.spp).mean(dim=2)
             if s.spp > 1:
                 V[f0:f0 + nf].view(nf, HW)[:, c0:c1] = ((Es - m[:, :, None]) ** 2).sum(dim=2) / (s.spp - 1)
             else:
@@ -402,7 +408,10 @@ def make_clip(spec: ClipSpec, device="cpu", frames: Optional[Sequence[int]] = No
             for f, name in enumerate(chans):
                 feat[f0:f0 + nf, f].view(nf, HW)[:, c0:c1] = \
                     a[name].reshape(nf, n, s.spp).mean(dim=2).to(fdt)
-    return dict(E=E, var=V, feat=feat, spec=s)
+    out = dict(E=E, var=V, feat=feat, spec=s)
+    if reference:
+        out["E_ref"] = E_ref
+    return out
 
 
 def random_features_clip(W: int, H: int, T: int, F: int, seed: int, device="cpu",
