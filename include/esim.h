@@ -93,6 +93,14 @@ typedef struct {
                               W-normalised Gram (the alpha row is untouched)    */
   int32_t precision;       /* esim_precision                                    */
   double kappa_fp64;       /* ESIM_GRAM_F32C: bound on kappa-hat               */
+  int32_t multi_crossing;  /* exhaustive and raw modes: 0 = at most one event per
+                              pixel-frame, L_ref reset to the current value (the
+                              paper's fixed-interval ESIM, Sec. 3); 1 = ESIM with
+                              every crossing: n = floor(|L - L_ref| / C) events,
+                              the brightness taken as linear between frames, at
+                              the fractional times the levels L_ref + k p C are
+                              passed, and L_ref <- L_ref + n p C.  Needs the
+                              state's `last`.  Ignored by the thresholded mode. */
 } esim_params;
 
 /* Per-pixel reference state (Sec. 2.2: one regression model per pixel, kept
@@ -104,12 +112,17 @@ typedef struct {
   float* beta;             /* [F][H*W]                                           */
   float* xref;             /* [F][H*W]  feature vector at the last event          */
   int32_t* tref;           /* [H*W]     frame of the last event                    */
+  float* last;             /* [H*W]     compared value of the previous frame
+                              (multi_crossing only; nullable otherwise)         */
 } esim_state;
 
-/* Event sink.  Events are appended in (t, clip, py, px) order at *count; an
- * event whose index reaches `capacity` is dropped but still counted, so a
- * caller detects overflow by *count > capacity after synchronising.
- * `clip` may be NULL.  Timestamps are frame indices (time = t * dt). */
+/* Event sink.  Events are appended in (t, clip, py, px) order at *count (the
+ * events of one pixel-frame in time order); an event whose index reaches
+ * `capacity` is dropped but still counted, so a caller detects overflow by
+ * *count > capacity after synchronising.  `clip` and `ts` may be NULL.
+ * Timestamps are frame indices (time = t * dt); `ts` receives the event's
+ * time in frame units: t itself, or with multi_crossing the interpolated
+ * crossing time in (t - 1, t]. */
 typedef struct {
   int32_t* x;
   int32_t* y;
@@ -118,6 +131,7 @@ typedef struct {
   int32_t* clip;
   int64_t capacity;
   int64_t* count;          /* device, running total                             */
+  float* ts;               /* nullable: time of each event in frame units       */
 } esim_events_buf;
 
 typedef struct esim_plan_s* esim_plan;

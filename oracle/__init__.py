@@ -249,3 +249,47 @@ def backward(clip: Clip, p: Params, items: np.ndarray, galpha: np.ndarray):
     fails = _L().orc_backward(ctypes.byref(clip._c), ctypes.byref(cp), items.ctypes.data,
                               items.size, galpha.ctypes.data, gy.ctypes.data, gb.ctypes.data)
     return gy, gb, fails
+
+
+def esim_multi_crossing(L: np.ndarray, C: float, W: int):
+    """ESIM with every crossing (the event rule of Sec. 1.1 eq. 1 applied to each
+    level L_ref + k p C the brightness passes between two frames, the
+    brightness taken as linear between the frames):
+
+      at t = 0:  L_ref = L_last = L_0, no events
+      at t >= 1: d = L_t - L_ref, n = floor(|d| / C), p = sign d; for k = 1..n
+                 an event (x, y, t, p) at the fractional time
+                 (t - 1) + (L_ref + k p C - L_last) / (L_t - L_last);
+                 L_ref <- L_ref + n p C (stored in FP32, like the state),
+                 L_last <- L_t.
+
+    L: [T][npix] values as stored (FP32); C and the arithmetic in FP64, each
+    product and sum rounded on its own.  Returns dict of
+    x, y, t, p, ts in (t, pixel, k) order."""
+    L = np.asarray(L, dtype=np.float32)
+    T, npix = L.shape
+    Cd = float(C)
+    Lref = L[0].copy()
+    Llast = L[0].copy()
+    xs, ys, ts_, ps, fts = [], [], [], [], []
+    for t in range(1, T):
+        cur = L[t]
+        d = cur.astype(np.float64) - Lref.astype(np.float64)
+        n = np.floor(np.abs(d) / Cd).astype(np.int64)
+        pol = np.where(d > 0, 1, -1)
+        for q in np.nonzero(n >= 1)[0]:
+            pq = int(pol[q])
+            den = float(cur[q]) - float(Llast[q])
+            for k in range(1, int(n[q]) + 1):
+                level = float(Lref[q]) + k * (pq * Cd)
+                xs.append(q % W)
+                ys.append(q // W)
+                ts_.append(t)
+                ps.append(pq)
+                fts.append(np.float32((t - 1) + (level - float(Llast[q])) / den))
+        upd = n >= 1
+        Lref = np.where(upd, (Lref.astype(np.float64) + n * (pol * Cd)).astype(np.float32), Lref)
+        Llast = cur.copy()
+    return dict(x=np.array(xs, np.int32), y=np.array(ys, np.int32), t=np.array(ts_, np.int32),
+                p=np.array(ps, np.int8), ts=np.array(fts, np.float32), count=len(xs))
+

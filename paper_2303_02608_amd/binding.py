@@ -41,18 +41,18 @@ class esim_params(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("tr", ctypes.c_int32), ("C", ctypes.c_double),
                 ("h", ctypes.c_double), ("b", ctypes.c_double * MAX_D),
                 ("ridge", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("kappa_fp64", ctypes.c_double)]
+                ("kappa_fp64", ctypes.c_double), ("multi_crossing", ctypes.c_int32)]
 
 
 class esim_state(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p),
-                ("xref", ctypes.c_void_p), ("tref", ctypes.c_void_p)]
+                ("xref", ctypes.c_void_p), ("tref", ctypes.c_void_p), ("last", ctypes.c_void_p)]
 
 
 class esim_events_buf(ctypes.Structure):
     _fields_ = [("x", ctypes.c_void_p), ("y", ctypes.c_void_p), ("t", ctypes.c_void_p),
                 ("p", ctypes.c_void_p), ("clip", ctypes.c_void_p),
-                ("capacity", ctypes.c_int64), ("count", ctypes.c_void_p)]
+                ("capacity", ctypes.c_int64), ("count", ctypes.c_void_p), ("ts", ctypes.c_void_p)]
 
 
 # Every symbol the header declares, with (restype, argtypes).
@@ -125,10 +125,11 @@ class Params:
 
     def __init__(self, r: int, tr: int, C: float, h: float = 1.0,
                  b: Optional[Sequence[float]] = None, ridge: float = 1e-6,
-                 precision: int = GRAM_F64, kappa_fp64: float = 1e6):
+                 precision: int = GRAM_F64, kappa_fp64: float = 1e6, multi_crossing: bool = False):
         self.r, self.tr, self.C, self.h = int(r), int(tr), float(C), float(h)
         self.b = None if b is None else [float(v) for v in b]
         self.ridge, self.precision, self.kappa_fp64 = float(ridge), int(precision), float(kappa_fp64)
+        self.multi_crossing = bool(multi_crossing)
 
     def struct(self, F: int) -> esim_params:
         b = [1.0] * (F + 2) if self.b is None else list(self.b)
@@ -136,7 +137,7 @@ class Params:
             raise ValueError(f"b needs F+2 = {F + 2} values")
         arr = (ctypes.c_double * MAX_D)(*(b + [1.0] * (MAX_D - len(b))))
         return esim_params(self.r, self.tr, self.C, self.h, arr, self.ridge, self.precision,
-                           self.kappa_fp64)
+                           self.kappa_fp64, int(self.multi_crossing))
 
 
 class State:
@@ -148,9 +149,11 @@ class State:
         self.beta = torch.zeros((F, HW), dtype=torch.float32, device=device)
         self.xref = torch.zeros((F, HW), dtype=torch.float32, device=device)
         self.tref = torch.zeros(HW, dtype=torch.int32, device=device)
+        self.last = torch.zeros(HW, dtype=torch.float32, device=device)
 
     def struct(self) -> esim_state:
-        return esim_state(_ptr(self.alpha), _ptr(self.beta), _ptr(self.xref), _ptr(self.tref))
+        return esim_state(_ptr(self.alpha), _ptr(self.beta), _ptr(self.xref), _ptr(self.tref),
+                          _ptr(self.last))
 
 
 class Plan:
@@ -203,18 +206,19 @@ class Plan:
 class Events:
     """Device event buffers (SoA) with a running count."""
 
-    def __init__(self, capacity: int, device, with_clip: bool = False):
+    def __init__(self, capacity: int, device, with_clip: bool = False, with_ts: bool = False):
         self.capacity = int(capacity)
         self.x = torch.empty(self.capacity, dtype=torch.int32, device=device)
         self.y = torch.empty(self.capacity, dtype=torch.int32, device=device)
         self.t = torch.empty(self.capacity, dtype=torch.int32, device=device)
         self.p = torch.empty(self.capacity, dtype=torch.int8, device=device)
         self.clip = torch.empty(self.capacity, dtype=torch.int32, device=device) if with_clip else None
+        self.ts = torch.empty(self.capacity, dtype=torch.float32, device=device) if with_ts else None
         self.count = torch.zeros(1, dtype=torch.int64, device=device)
 
     def struct(self) -> esim_events_buf:
         return esim_events_buf(_ptr(self.x), _ptr(self.y), _ptr(self.t), _ptr(self.p),
-                               _ptr(self.clip), self.capacity, _ptr(self.count))
+                               _ptr(self.clip), self.capacity, _ptr(self.count), _ptr(self.ts))
 
     def host(self):
         n = int(self.count.item())
@@ -223,6 +227,8 @@ class Events:
                    t=self.t[:m].cpu().numpy(), p=self.p[:m].cpu().numpy(), count=n)
         if self.clip is not None:
             out["clip"] = self.clip[:m].cpu().numpy()
+        if self.ts is not None:
+            out["ts"] = self.ts[:m].cpu().numpy()
         return out
 
 

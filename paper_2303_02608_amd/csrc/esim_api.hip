@@ -88,6 +88,13 @@ int launch_plan_regress(esim_plan pl, int32_t t, const int64_t* worklist, const 
                    "regress");
 }
 
+// The every-crossing rule keeps the previous frame's value in the state.
+bool multi_state_ok(esim_plan pl) {
+  for (const auto& c : pl->host)
+    if (c.multi && !c.st_last) return false;
+  return true;
+}
+
 bool full_state(esim_plan pl) {
   for (const auto& c : pl->host)
     if (!c.st_beta || !c.st_xref || !c.st_alpha || !c.st_tref) return false;
@@ -179,6 +186,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
         cd.st_beta = states[c].beta;
         cd.st_xref = states[c].xref;
         cd.st_tref = states[c].tref;
+        cd.st_last = states[c].last;
       }
       cd.W = k.W;
       cd.H = k.H;
@@ -188,6 +196,11 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       cd.r = p.r;
       cd.tr = p.tr;
       cd.precision = p.precision;
+      if (p.multi_crossing != 0 && p.multi_crossing != 1) {
+        delete pl;
+        return fail(ESIM_E_INVAL, "multi_crossing must be 0 or 1");
+      }
+      cd.multi = p.multi_crossing;
       cd.HW = static_cast<int64_t>(k.W) * k.H;
       cd.pix_off = pix;
       cd.blk_off = blk;
@@ -403,7 +416,7 @@ int esim_events(esim_plan pl, int32_t t, int32_t mode, const int64_t* worklist, 
     }
     if (!ev || !ev->x || !ev->y || !ev->t || !ev->p || !ev->count || ev->capacity < 0)
       return fail(ESIM_E_INVAL, "events buffer incomplete");
-    esim::EventsDev ed{ev->x, ev->y, ev->t, ev->p, ev->clip, ev->capacity, ev->count};
+    esim::EventsDev ed{ev->x, ev->y, ev->t, ev->p, ev->clip, ev->capacity, ev->count, ev->ts};
     if (mode == ESIM_THRESHOLDED) {
       if (!worklist || !count || !dl || !alpha || !beta)
         return fail(ESIM_E_INVAL, "thresholded events need worklist, count, dl, alpha and beta");
@@ -415,6 +428,7 @@ int esim_events(esim_plan pl, int32_t t, int32_t mode, const int64_t* worklist, 
                        "events(thresholded)");
     }
     if (mode == ESIM_EXHAUSTIVE || mode == ESIM_RAW) {
+      if (!multi_state_ok(pl)) return fail(ESIM_E_INVAL, "multi_crossing needs the state's last");
       if (mode == ESIM_EXHAUSTIVE && (!alpha || n_out < pl->npix))
         return fail(ESIM_E_INVAL, "exhaustive events need dense alpha (n_out >= plan pixels)");
       return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t,
@@ -445,7 +459,7 @@ int esim_step(esim_plan pl, int32_t t, int32_t mode, float* dl, esim_events_buf*
                                  true, s);
     if (!ev || !ev->x || !ev->y || !ev->t || !ev->p || !ev->count || ev->capacity < 0)
       return fail(ESIM_E_INVAL, "events buffer incomplete");
-    esim::EventsDev ed{ev->x, ev->y, ev->t, ev->p, ev->clip, ev->capacity, ev->count};
+    esim::EventsDev ed{ev->x, ev->y, ev->t, ev->p, ev->clip, ev->capacity, ev->count, ev->ts};
     if (mode == ESIM_THRESHOLDED) {
       int rc = hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold,
                                                    dl, nullptr, pl->ws, pl->step_wl,
@@ -455,6 +469,8 @@ int esim_step(esim_plan pl, int32_t t, int32_t mode, float* dl, esim_events_buf*
       return launch_plan_regress(pl, t, pl->step_wl, pl->step_count, pl->wl_capacity, nullptr, nullptr,
                                  nullptr, nullptr, true, s);
     }
+    if ((mode == ESIM_EXHAUSTIVE || mode == ESIM_RAW) && !multi_state_ok(pl))
+      return fail(ESIM_E_INVAL, "multi_crossing needs the state's last");
     if (mode == ESIM_EXHAUSTIVE) {
       int rc = launch_plan_regress(pl, t, nullptr, nullptr, pl->npix, pl->step_alpha, nullptr, nullptr,
                                    nullptr, false, s);

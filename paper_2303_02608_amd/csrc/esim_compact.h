@@ -16,6 +16,7 @@ struct EventsDev {
   int32_t* clip;
   int64_t capacity;
   int64_t* count;
+  float* ts;
 };
 
 hipError_t launch_log(const float* E, float* y, int64_t n, float eps, hipStream_t s);

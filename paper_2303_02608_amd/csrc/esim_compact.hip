@@ -44,6 +44,29 @@ __global__ void __launch_bounds__(256) log_kernel(const float* __restrict__ E, f
     y[i] = logf(E[i] + eps);
 }
 
+// Levels L_ref + k p C passed by a change d (every-crossing rule): floor(|d| / C).
+__device__ __forceinline__ int crossings(double d, double C) {
+  const double n = floor(fabs(d) / C);
+  return n >= 1.0 ? static_cast<int>(fmin(n, 2147483647.0)) : 0;
+}
+
+// Exclusive prefix of one int per thread of a kBlock-thread block.
+__device__ int block_exclusive_scan(int v) {
+  __shared__ int wsum[kWavesPerBlock];
+  const int lane = threadIdx.x & (kWave - 1), w = threadIdx.x / kWave;
+  int x = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const int y = __shfl_up(x, o);
+    if (lane >= o) x += y;
+  }
+  if (lane == kWave - 1) wsum[w] = x;
+  __syncthreads();
+  int before = 0;
+  for (int k = 0; k < w; ++k) before += wsum[k];
+  return before + x - v;
+}
+
 __global__ void __launch_bounds__(kBlock)
 flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, float* __restrict__ dl,
             const float* __restrict__ alpha, Workspace ws, const int64_t* __restrict__ ev_count) {
@@ -54,6 +77,7 @@ flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, floa
   const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
   const bool in = p < C.HW && t >= 0 && t < C.T;
   bool flag = false, pos = false;
+  int ncross = 0;
   if (in) {
     float val = __builtin_nanf("");
     if (mode == kFlagThreshold) {
@@ -73,10 +97,16 @@ flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, floa
                                               : C.y[static_cast<int64_t>(t) * C.HW + p];
       if (t == 0) {
         C.st_alpha[p] = L;
+        if (C.multi) C.st_last[p] = L;
       } else {
         const double d = static_cast<double>(L) - static_cast<double>(C.st_alpha[p]);
         val = static_cast<float>(d);
-        if (fabs(d) >= C.C) {
+        if (C.multi) {
+          // every crossing: the scatter writes the events and updates the state
+          ncross = crossings(d, C.C);
+          flag = ncross > 0;
+          pos = d > 0.0;
+        } else if (fabs(d) >= C.C) {
           flag = true;
           pos = d > 0.0;
           C.st_alpha[p] = L;
@@ -88,10 +118,16 @@ flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, floa
   const int w = threadIdx.x / kWave;
   const uint64_t fm = __ballot(flag);
   const uint64_t pm = __ballot(flag && pos);
+  int wc = __popcll(fm);
+  if (C.multi && mode != kFlagThreshold) {   // uniform: one clip per block
+    wc = ncross;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) wc += __shfl_xor(wc, o);
+  }
   if ((threadIdx.x & (kWave - 1)) == 0) {
     ws.flags[b * kWavesPerBlock + w] = fm;
     ws.pol[b * kWavesPerBlock + w] = pm;
-    wcount[w] = __popcll(fm);
+    wcount[w] = wc;
   }
   __syncthreads();
   if (threadIdx.x == 0) {
@@ -138,7 +174,8 @@ __global__ void __launch_bounds__(kBlock) chunk_kernel(Workspace ws, int64_t nbl
 
 __global__ void __launch_bounds__(kBlock)
 scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, Workspace ws, int chunked,
-               int64_t* __restrict__ worklist, int32_t* __restrict__ count, EventsDev ev) {
+               const float* __restrict__ alpha, int64_t* __restrict__ worklist, int32_t* __restrict__ count,
+               EventsDev ev) {
   const int64_t b = blockIdx.x;
   const int64_t off0 = counts_before(ws, b, chunked != 0);
   const int64_t base = ws.misc[0];
@@ -154,6 +191,42 @@ scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, W
   const ClipDev& C = clips[cl];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
+  if (C.multi && mode != kFlagThreshold) {   // uniform: one clip per block
+    // every-crossing rule: n events per pixel at the interpolated times the
+    // levels L_ref + k p C are passed; then L_ref += n p C and L_last = L
+    const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
+    const bool in = p < C.HW && t >= 1 && t < C.T;
+    float L = 0.0f, Lref = 0.0f, Llast = 0.0f;
+    int n = 0;
+    if (in) {
+      L = mode == kFlagExhaustive ? alpha[C.pix_off + p] : C.y[static_cast<int64_t>(t) * C.HW + p];
+      Lref = C.st_alpha[p];
+      Llast = C.st_last[p];
+      n = crossings(static_cast<double>(L) - static_cast<double>(Lref), C.C);
+    }
+    const int64_t off = off0 + block_exclusive_scan(n);
+    if (n > 0) {
+      const double d = static_cast<double>(L) - static_cast<double>(Lref);
+      const int pol = d > 0.0 ? 1 : -1;
+      const double step = pol * C.C;               // exact: C times +-1
+      const double den = static_cast<double>(L) - static_cast<double>(Llast);
+      for (int k = 1; k <= n; ++k) {
+        const int64_t e = base + off + (k - 1);
+        if (e >= ev.capacity) break;
+        // two roundings (no fused multiply-add), as the definition is written
+        const double level = __dadd_rn(static_cast<double>(Lref), __dmul_rn(static_cast<double>(k), step));
+        ev.x[e] = static_cast<int32_t>(p % C.W);
+        ev.y[e] = static_cast<int32_t>(p / C.W);
+        ev.t[e] = t;
+        ev.p[e] = static_cast<int8_t>(pol);
+        if (ev.clip) ev.clip[e] = cl;
+        if (ev.ts) ev.ts[e] = static_cast<float>((t - 1) + (level - static_cast<double>(Llast)) / den);
+      }
+      C.st_alpha[p] = static_cast<float>(__dadd_rn(static_cast<double>(Lref), __dmul_rn(static_cast<double>(n), step)));
+    }
+    if (in) C.st_last[p] = L;
+    return;
+  }
   const uint64_t m = ws.flags[b * kWavesPerBlock + w];
   if (!((m >> lane) & 1ull)) return;
   const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
@@ -170,6 +243,7 @@ scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, W
       ev.t[e] = t;
       ev.p[e] = pos ? 1 : -1;
       if (ev.clip) ev.clip[e] = cl;
+      if (ev.ts) ev.ts[e] = static_cast<float>(t);
     }
   }
 }
@@ -219,6 +293,7 @@ __device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, 
       ev.t[e] = t;
       ev.p[e] = d > 0.0f ? 1 : -1;
       if (ev.clip) ev.clip[e] = cl;
+      if (ev.ts) ev.ts[e] = static_cast<float>(t);
     }
     C.st_alpha[p] = alpha[i];
     for (int f = 0; f < C.F; ++f) {
@@ -272,7 +347,7 @@ hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, i
                        dim3(kBlock), 0, s, ws, nblk);
   EventsDev none{};
   hipLaunchKernelGGL(scatter_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
-                     t, mode, ws, chunked, wl, wl ? count : nullptr, ev ? *ev : none);
+                     t, mode, ws, chunked, alpha, wl, wl ? count : nullptr, ev ? *ev : none);
   return hipGetLastError();
 }
 

@@ -22,8 +22,10 @@ struct ClipDev {
   float* st_beta;          // [F][HW]
   float* st_xref;          // [F][HW]
   int32_t* st_tref;        // [HW]
+  float* st_last;          // [HW] previous frame's compared value (multi-crossing)
   int32_t W, H, T, F;
   int32_t feat_f16, r, tr, precision;
+  int32_t multi;           // every-crossing event rule in the exhaustive/raw modes
   int64_t HW;
   int64_t pix_off;         // first pixel in the concatenated pixel range
   int64_t blk_off;         // first kBlock-pixel block of the flag/scatter grid

@@ -43,7 +43,8 @@ class Simulator:
         self.beta = torch.empty((F + 2, self.HW), dtype=torch.float32, device=dev)
         if capacity is None:
             capacity = min(T * self.HW, 1 << 26)
-        self.ev = B.Events(capacity, dev)
+        # every-crossing events carry their interpolated times
+        self.ev = B.Events(capacity, dev, with_ts=params.multi_crossing)
         # per-frame flagged counts (only recorded when asked: it adds a copy per frame)
         self.flagged = torch.zeros(T, dtype=torch.int32, device=dev)
         self.graph = None
