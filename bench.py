@@ -470,6 +470,17 @@ def main():
                              "tflops": round(fl_dense / (dense_ms.sum() * 1e-3) / 1e12, 3)}}
     log(f"regress list launches: {list_ms.size}, avg {list_ms.mean():.4f} ms, {achieved:.2f} TFLOP/s; "
         f"dense frame 0: {dense_ms.sum():.3f} ms")
+    # End to end: the time the step would take at the bounding roofline of each
+    # part -- regression FLOPs at the FP64 issue peak, plus the HBM-bound
+    # steps' algorithmic bytes at 8 TB/s (log 8 B per pixel-frame; threshold
+    # 3F*4 + 4 B per pixel-frame t >= 1; compaction 8 B work list + 13 B event
+    # per flagged pixel) -- divided by the measured step.
+    flops = fl_dense + fl_list
+    hbm = 8.0 * T * H * W + (3 * F * 4 + 4) * (T - 1) * H * W + 21.0 * ev["count"]
+    bound_ms = (flops / (PEAK_ALU_TFLOPS * 1e12) + hbm / (PEAK_HBM_GBS * 1e9)) * 1e3
+    roof["end_to_end"] = {"bound_ms": round(bound_ms, 3), "measured_ms": round(ms_thr, 3),
+                          "frac": round(bound_ms / ms_thr, 4),
+                          "model": "regression FLOP at 78.6 TFLOP/s + HBM-bound bytes at 8 TB/s"}
 
     # ---- dense (exhaustive) regression roofline, same method ---------------
     if exh is not None:
