@@ -99,8 +99,9 @@ typedef struct {
                               every crossing: n = floor(|L - L_ref| / C) events,
                               the brightness taken as linear between frames, at
                               the fractional times the levels L_ref + k p C are
-                              passed, and L_ref <- L_ref + n p C.  Needs the
-                              state's `last`.  Ignored by the thresholded mode. */
+                              passed, and L_ref <- L_ref + n p C (n capped at
+                              2^20 per pixel-frame).  Needs the state's `last`.
+                              Ignored by the thresholded mode.                  */
 } esim_params;
 
 /* Per-pixel reference state (Sec. 2.2: one regression model per pixel, kept

@@ -257,7 +257,7 @@ def esim_multi_crossing(L: np.ndarray, C: float, W: int):
     brightness taken as linear between the frames):
 
       at t = 0:  L_ref = L_last = L_0, no events
-      at t >= 1: d = L_t - L_ref, n = floor(|d| / C), p = sign d; for k = 1..n
+      at t >= 1: d = L_t - L_ref, n = min(floor(|d| / C), 2^20), p = sign d; for k = 1..n
                  an event (x, y, t, p) at the fractional time
                  (t - 1) + (L_ref + k p C - L_last) / (L_t - L_last);
                  L_ref <- L_ref + n p C (stored in FP32, like the state),
@@ -275,7 +275,7 @@ def esim_multi_crossing(L: np.ndarray, C: float, W: int):
     for t in range(1, T):
         cur = L[t]
         d = cur.astype(np.float64) - Lref.astype(np.float64)
-        n = np.floor(np.abs(d) / Cd).astype(np.int64)
+        n = np.minimum(np.floor(np.abs(d) / Cd), 2.0 ** 20).astype(np.int64)   # cap of the option
         pol = np.where(d > 0, 1, -1)
         for q in np.nonzero(n >= 1)[0]:
             pq = int(pol[q])

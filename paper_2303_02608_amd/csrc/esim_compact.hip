@@ -44,10 +44,12 @@ __global__ void __launch_bounds__(256) log_kernel(const float* __restrict__ E, f
     y[i] = logf(E[i] + eps);
 }
 
-// Levels L_ref + k p C passed by a change d (every-crossing rule): floor(|d| / C).
+// Levels L_ref + k p C passed by a change d (every-crossing rule): floor(|d| / C),
+// at most kMaxCrossings (so that block and wave sums of counts stay in int32).
+constexpr double kMaxCrossings = 1048576.0;
 __device__ __forceinline__ int crossings(double d, double C) {
   const double n = floor(fabs(d) / C);
-  return n >= 1.0 ? static_cast<int>(fmin(n, 2147483647.0)) : 0;
+  return n >= 1.0 ? static_cast<int>(fmin(n, kMaxCrossings)) : 0;
 }
 
 // Exclusive prefix of one int per thread of a kBlock-thread block.
