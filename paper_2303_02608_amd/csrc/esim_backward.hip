@@ -178,40 +178,58 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   double acc = 0.0;
   const int t0 = max(0, tq - tr), t1 = min(T - 1, tq + tr);
   const int y0 = max(0, yq - r), y1 = min(H - 1, yq + r);
-  for (int tc = t0; tc <= t1; ++tc)
-    for (int yc = y0; yc <= y1; ++yc) {
-      const int32_t* row = bd.item_map + static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W;
-      for (int k = threadIdx.x; k < seg; k += kGatherTile) {
-        const int x = xs + k;
-        mrow[k] = (x >= 0 && x < W) ? row[x] : -1;
-      }
-      __syncthreads();
-      // each wave walks the present items of its 64-column chunks (a
-      // wave-uniform loop over the ballot); lanes m < span load the item's
-      // slots m, one coalesced 4 (2r + 1)-byte read per item
-      const int64_t sbase = static_cast<int64_t>((tq - tc + tr) * span + (yq - yc + r)) * span;
-      for (int base = wave * kWave; base < seg; base += kGatherTile) {
-        const int c = base + lane;
-        const int32_t it = c < seg ? mrow[c] : -1;
-        uint64_t mask = __ballot(it >= 0);
-        while (mask != 0) {
-          const int bit = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-          mask &= mask - 1;
-          const int32_t itc = __shfl(it, bit);
-          for (int m = lane; m < span; m += kWave)
-            cx[(base + bit) * span + m] = bd.contrib[static_cast<int64_t>(itc) * bd.S + sbase + m];
-        }
-      }
-      __syncthreads();
-      if (xq < W) {
-        // items at xc = xq - r + m (staged index threadIdx.x + m), slot x-index span - 1 - m
-        for (int m = 0; m < span; ++m) {
-          const int c = static_cast<int>(threadIdx.x) + m;
-          if (mrow[c] >= 0) acc += static_cast<double>(cx[c * span + (span - 1 - m)]);
-        }
-      }
-      __syncthreads();
+  // item rows (tc, yc) in ascending order, k = (tc - t0) * ny + (yc - y0); the
+  // map entries of row k + 1 are loaded into registers while row k is used
+  const int ny = y1 - y0 + 1;
+  const int nrow = (t1 - t0 + 1) * ny;
+  constexpr int kPer = 2;                              // staged columns per thread (seg <= 2 tile)
+  auto load_map = [&](int k, int32_t (&v)[kPer]) {
+    const int tc = t0 + k / ny, yc = y0 + k % ny;
+    const int32_t* row = bd.item_map + static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int c = static_cast<int>(threadIdx.x) + q * kGatherTile;
+      const int x = xs + c;
+      v[q] = (c < seg && x >= 0 && x < W) ? row[x] : -1;
     }
+  };
+  int32_t nxt[kPer];
+  if (nrow > 0) load_map(0, nxt);
+  for (int k = 0; k < nrow; ++k) {
+    const int tc = t0 + k / ny, yc = y0 + k % ny;
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int c = static_cast<int>(threadIdx.x) + q * kGatherTile;
+      if (c < seg) mrow[c] = nxt[q];
+    }
+    __syncthreads();
+    if (k + 1 < nrow) load_map(k + 1, nxt);
+    // each wave walks the present items of its 64-column chunks (a
+    // wave-uniform loop over the ballot); lanes m < span load the item's
+    // slots m, one coalesced 4 (2r + 1)-byte read per item
+    const int64_t sbase = static_cast<int64_t>((tq - tc + tr) * span + (yq - yc + r)) * span;
+    for (int base = wave * kWave; base < seg; base += kGatherTile) {
+      const int c = base + lane;
+      const int32_t it = c < seg ? mrow[c] : -1;
+      uint64_t mask = __ballot(it >= 0);
+      while (mask != 0) {
+        const int bit = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+        mask &= mask - 1;
+        const int32_t itc = __shfl(it, bit);
+        for (int m = lane; m < span; m += kWave)
+          cx[(base + bit) * span + m] = bd.contrib[static_cast<int64_t>(itc) * bd.S + sbase + m];
+      }
+    }
+    __syncthreads();
+    if (xq < W) {
+      // items at xc = xq - r + m (staged index threadIdx.x + m), slot x-index span - 1 - m
+      for (int m = 0; m < span; ++m) {
+        const int c = static_cast<int>(threadIdx.x) + m;
+        if (mrow[c] >= 0) acc += static_cast<double>(cx[c * span + (span - 1 - m)]);
+      }
+    }
+    __syncthreads();
+  }
   if (xq < W && acc != 0.0) g_y[rowq * W + xq] += static_cast<float>(acc);
 }
 
