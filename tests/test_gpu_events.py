@@ -272,3 +272,24 @@ def test_step_without_dl(small_clip):
     assert ea["count"] == eb["count"] > 0
     for k in ("x", "y", "t", "p"):
         assert np.array_equal(ea[k], eb[k])
+
+
+@pytest.mark.parametrize("W,H,T,r,tr", [
+    (1, 37, 6, 3, 1),      # one column
+    (41, 1, 6, 3, 1),      # one row
+    (5, 4, 7, 9, 2),       # window wider than the image in every direction
+    (17, 13, 1, 2, 1),     # a single frame: initialisation only
+])
+def test_degenerate_shapes_match_oracle(W, H, T, r, tr):
+    """Degenerate clip shapes: every mode's events equal the oracle's."""
+    d = synth.random_features_clip(W, H, T, 3, seed=31 + W + H)
+    E, feat = d["E"].numpy(), d["feat"].numpy()
+    p = B.Params(r=r, tr=tr, C=0.05)
+    say(f"degenerate shape {W}x{H}x{T} r={r} tr={tr}")
+    for mode in ("thresholded", "exhaustive", "raw"):
+        gpu, _ = run_gpu(E, feat, p, mode)
+        orc = _oracle_run(E, feat, p, mode)
+        n, excused, fails = compare_events(gpu, orc, W, p.C, BAND)
+        assert not fails and excused <= 1, (mode, fails[:5])
+        if T == 1:
+            assert gpu["count"] == 0
