@@ -293,3 +293,21 @@ def test_degenerate_shapes_match_oracle(W, H, T, r, tr):
         assert not fails and excused <= 1, (mode, fails[:5])
         if T == 1:
             assert gpu["count"] == 0
+
+
+@pytest.mark.parametrize("F,feat_dtype,r,tr", [(1, "f32", 4, 1), (12, "f32", 3, 1), (7, "f16", 5, 1),
+                                              (10, "f16", 8, 2)])
+def test_thresholded_feature_counts_and_f16(F, feat_dtype, r, tr):
+    """The thresholded path at the extreme feature counts and with FP16
+    feature storage (the oracle decodes the same FP16 bits)."""
+    W, H, T = 48, 40, 8
+    d = synth.random_features_clip(W, H, T, F, seed=40 + F, feat_dtype=feat_dtype)
+    E, feat = d["E"].numpy(), d["feat"].numpy()
+    p = B.Params(r=r, tr=tr, C=0.1)
+    say(f"thresholded F={F} {feat_dtype} r={r} tr={tr}")
+    gpu, _ = run_gpu(E, feat, p, "thresholded")
+    orc = _oracle_run(E, feat, p, "thresholded")
+    n, excused, fails = compare_events(gpu, orc, W, p.C, BAND)
+    say(f"gpu {gpu['count']} oracle {orc['count']} excused {excused}")
+    assert gpu["count"] > 0
+    assert not fails and excused <= max(2, n // 1000), fails[:5]
