@@ -14,8 +14,10 @@ pytestmark = pytest.mark.gpu
 
 
 def _clips():
+    # radii up to 9: a work list with 16 lanes per item then mixes the one-pass
+    # instance (windows of at most 16 columns) with the general one
     shapes = [(40, 30, 9, 3, 1), (64, 48, 6, 2, 1), (23, 57, 12, 4, 0), (50, 50, 3, 3, 1),
-              (64, 64, 10, 5, 1)]
+              (64, 64, 10, 5, 1), (36, 28, 5, 9, 1)]
     out = []
     for i, (W, H, T, r, tr) in enumerate(shapes):
         spec = synth.ClipSpec(W=W, H=H, T=T, spp=2 + i, F=7, n_discs=2 + i, speed=(0.5, 2.0),
