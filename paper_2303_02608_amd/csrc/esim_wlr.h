@@ -172,65 +172,18 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
   }
 }
 
-// Normal equations of one item, accumulated per lane (Gram entries with a v_x
-// factor are folded once per column pass).
+// Normal equations of one item, accumulated per lane.  Within a column pass
+// v_x is constant in a lane, so the entries with a v_x factor are not summed
+// per sample: they are v_x times sums of the first-row entries (formed once per
+// item by the one-pass form, once per pass by the pass-snapshot form).
 template <int F, class Real = double>
 struct Gram {
   static constexpr int NA = F * (F + 1) / 2;
   Real SW, A0y, g0, A0f[F];
   Real A0x, Axx, Axy, gx, Axf[F];
   Real Ayy, gy, Syy, Ayf[F], gf[F], Aff[NA];
-  Real qW, qY, qG, qF[F];
+  Real qW, qY, qG, qF[F];                 // first-row totals at the pass start
 
-  __device__ __forceinline__ void zero() {
-    SW = A0y = g0 = A0x = Axx = Axy = gx = Ayy = gy = Syy = 0;
-#pragma unroll
-    for (int f = 0; f < F; ++f) A0f[f] = Axf[f] = Ayf[f] = gf[f] = 0;
-#pragma unroll
-    for (int k = 0; k < NA; ++k) Aff[k] = 0;
-  }
-  __device__ __forceinline__ void pass_begin() {
-    qW = qY = qG = 0;
-#pragma unroll
-    for (int f = 0; f < F; ++f) qF[f] = 0;
-  }
-  __device__ __forceinline__ void add(Real w, Real yd, const Real (&v)[F], Real vy) {
-    const Real wy = w * yd;
-    const Real wvy = w * vy;
-    qW += w;
-    qY += wvy;
-    qG += wy;
-    Ayy = fma(wvy, vy, Ayy);
-    gy = fma(wy, vy, gy);
-    Syy = fma(wy, yd, Syy);
-    int qq = 0;
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const Real wz = w * v[f];
-      qF[f] += wz;
-      Ayf[f] = fma(wvy, v[f], Ayf[f]);
-      gf[f] = fma(wz, yd, gf[f]);
-#pragma unroll
-      for (int e = f; e < F; ++e) {
-        Aff[qq] = fma(wz, v[e], Aff[qq]);
-        ++qq;
-      }
-    }
-  }
-  __device__ __forceinline__ void pass_end(Real vx) {
-    SW += qW;
-    A0y += qY;
-    g0 += qG;
-    A0x = fma(vx, qW, A0x);
-    Axx = fma(vx * vx, qW, Axx);
-    Axy = fma(vx, qY, Axy);
-    gx = fma(vx, qG, gx);
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      A0f[f] += qF[f];
-      Axf[f] = fma(vx, qF[f], Axf[f]);
-    }
-  }
   // One-pass form (every lane owns a single window column): the column sums
   // are the totals, and the entries with a v_x factor are formed once after
   // the window loop, so they are not live during it.
