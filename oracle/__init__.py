@@ -23,6 +23,9 @@ _SRC = os.path.join(_HERE, "esim_oracle.cpp")
 _LIB = os.path.join(_HERE, "liboracle.so")
 
 THRESHOLDED, EXHAUSTIVE, RAW = 0, 1, 2
+# thresholded with Delta R = |R_hat - R| evaluated explicitly (eqs. 4 and 7):
+# R_hat over the last-event window, or over the current frame's window
+EXPLICIT_LAST, EXPLICIT_NEW = 3, 4
 
 
 def build(force: bool = False) -> str:
@@ -65,6 +68,8 @@ def _L():
         _lib.orc_regress_items.restype = i32
         _lib.orc_residual_hat.argtypes = [vp, vp, i32, i32, i32, vp, vp]
         _lib.orc_residual_hat.restype = dbl
+        _lib.orc_explicit.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
+        _lib.orc_explicit.restype = i32
         _lib.orc_cond.argtypes = [vp, i32]
         _lib.orc_cond.restype = dbl
         _lib.orc_run.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp,
@@ -193,6 +198,24 @@ def residual_hat(clip: Clip, p: Params, t_ref: int, px: int, py: int, xhat: np.n
     return float(Rh), float(R[0])
 
 
+def explicit(clip: Clip, p: Params, new_window: bool, t_ref: int, t: int, px: int, py: int,
+             theta: np.ndarray):
+    """Delta R of Sec. 2.2 evaluated explicitly for the plane theta = (alpha,
+    beta over D) regressed at (t_ref, py, px): R (eq. 4) over the plane's own
+    window and R_hat (eq. 7) over the last-event window, or (new_window) over
+    frame t's window centred at frame t's feature vector.  Returns dict(R,
+    R_hat, mean, change): mean is the weighted mean of the translated plane's
+    residuals, change = sign(mean) * sqrt(|R_hat - R|)."""
+    cp, b = _params(clip, p)
+    theta = np.ascontiguousarray(theta, dtype=np.float64)
+    assert theta.size == clip.P
+    out = np.empty(4)
+    rc = _L().orc_explicit(ctypes.byref(clip._c), ctypes.byref(cp), 1 if new_window else 0, t_ref, t,
+                           px, py, theta.ctypes.data, out.ctypes.data)
+    assert rc == 0, rc
+    return dict(R=float(out[0]), R_hat=float(out[1]), mean=float(out[2]), change=float(out[3]))
+
+
 def cond(A: np.ndarray) -> float:
     """2-norm condition number of a symmetric positive definite matrix (Jacobi)."""
     A = np.ascontiguousarray(A, dtype=np.float64)
@@ -202,7 +225,9 @@ def cond(A: np.ndarray) -> float:
 def run(clip: Clip, p: Params, mode: int = THRESHOLDED, pixels: Optional[np.ndarray] = None,
         want_dl: bool = False, check_identity: bool = False, cap: Optional[int] = None,
         nthreads: int = 0):
-    """Event simulation (Sec. 1.1 eq. 1; Sec. 2.2 Prop. 1; Sec. 3 baselines).
+    """Event simulation (Sec. 1.1 eq. 1; Sec. 2.2 Prop. 1; Sec. 3 baselines;
+    EXPLICIT_LAST / EXPLICIT_NEW: Sec. 2.2 with Delta R evaluated explicitly,
+    dl then holding sign * sqrt(Delta R)).
 
     Returns dict(events=(x, y, t, p) int arrays in (t, py, px) order, count,
     dl [T][npix] (if asked), nflag[T], state (alpha, beta[F][npix], xref, tref),

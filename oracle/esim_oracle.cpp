@@ -15,6 +15,9 @@
 //                          regression of y over a window of neighbours.
 //   * orc_residual_hat     Sec. 2.2, eq. (7): residual of the translated plane,
 //                          evaluated explicitly over the last-event window.
+//   * orc_explicit         Sec. 2.2, eq. (7) and the R of eq. (4) for a stored
+//                          plane, over the last-event window or (the other
+//                          reading) over the current frame's window.
 //   * orc_run              Sec. 1.1 eq. (1) event rule; Sec. 2.2 threshold
 //                          (Prop. 1, eqs. (8)-(9)); the baselines of Sec. 3
 //                          ("ESIM" on the noisy frames, "WLR+ESIM").
@@ -43,6 +46,17 @@
 //     frame, and the reference model is replaced by the new regression.
 //   - Exhaustive and raw baselines: L_ref starts at frame 0; an event fires
 //     when |L_t - L_ref| >= C, then L_ref <- L_t.
+//   - Explicit thresholds (an ablation of Prop. 1): Delta R = |R_hat - R| is
+//     evaluated from its definition instead of the closed form.  R is eq. (4)
+//     for the stored plane over its own (last-event) window.  R_hat is eq. (7)
+//     over either the last-event window (the reading above: then Delta R equals
+//     the closed form's dL^2) or the window of the current frame t centred at
+//     x_hat^c, with weights of eq. (5) about x_hat^c and the current samples
+//     (the other reading, which also sees brightness changes that the features
+//     do not explain).  The sign of an event is the sign of the weighted mean
+//     of the translated plane's residuals y^i - alpha - beta^T (x^i - x_hat^c),
+//     which over the last-event window equals dL; the compared change is
+//     sign * sqrt(Delta R), which equals dL in the first reading.
 #include <algorithm>
 #include <cmath>
 #include <cstdint>
@@ -292,6 +306,62 @@ double residual_hat(const Fit& fit, const double* xhat, int D) {
   return Rh / fit.W;
 }
 
+// R of eq. (4) for the plane theta (alpha, beta over D) over the window of
+// frame tw about centre features xw, and the translated plane's residuals
+// rhat_i = y^i - alpha - beta^T (x^i - xhat): returns their weighted mean and
+// mean square.  With xw = x^c (the plane's own centre) and tw = t_ref this is
+// eq. (7) over the last-event window; with xw = xhat and tw = t, over the
+// current frame's window (then R is not formed: the window is not the plane's).
+struct WindowResiduals {
+  double W = 0.0, R = 0.0, Rhat = 0.0, mean = 0.0;
+};
+
+WindowResiduals window_residuals(const Clip& cl, const orc_params* p, int tw, int py, int px,
+                                 const double* xw, const double* theta, const double* xhat) {
+  const int D = cl.c->F + 2;
+  WindowResiduals o;
+  std::vector<Sample> win = gather_window(cl, p, tw, py, px, xw);
+  double sr2 = 0.0, sh = 0.0, sh2 = 0.0;
+  for (const Sample& s : win) {
+    // s.z[1 + j] = x^i_j - xw_j
+    double pr = theta[0], ph = theta[0];
+    for (int j = 0; j < D; ++j) {
+      pr += theta[1 + j] * s.z[1 + j];
+      ph += theta[1 + j] * (s.z[1 + j] + xw[j] - xhat[j]);
+    }
+    const double r = s.yv - pr, rh = s.yv - ph;
+    o.W += s.w;
+    sr2 += s.w * r * r;
+    sh += s.w * rh;
+    sh2 += s.w * rh * rh;
+  }
+  o.R = sr2 / o.W;
+  o.Rhat = sh2 / o.W;
+  o.mean = sh / o.W;
+  return o;
+}
+
+// Explicit Delta R of the stored plane (theta, centre features at t_ref) at
+// frame t (new_window: 0 = last-event window, 1 = frame t's window).  Returns
+// the compared change sign(mean) * sqrt(|R_hat - R|); *dR receives |R_hat - R|.
+double explicit_change(const Clip& cl, const orc_params* p, int new_window, int tref, int t, int py,
+                       int px, const double* theta, double* dR) {
+  const int D = cl.c->F + 2;
+  std::vector<double> xc(D), xhat(D);
+  feature_vector(cl, p->r, tref, py, px, xc.data());
+  feature_vector(cl, p->r, t, py, px, xhat.data());
+  const WindowResiduals last = window_residuals(cl, p, tref, py, px, xc.data(), theta, xhat.data());
+  double Rhat = last.Rhat, mean = last.mean;
+  if (new_window) {
+    const WindowResiduals cur = window_residuals(cl, p, t, py, px, xhat.data(), theta, xhat.data());
+    Rhat = cur.Rhat;
+    mean = cur.mean;
+  }
+  const double d = std::fabs(Rhat - last.R);
+  *dR = d;
+  return (mean > 0.0 ? 1.0 : -1.0) * std::sqrt(d);
+}
+
 int nthreads_or_default(int n) {
 #ifdef _OPENMP
   return n > 0 ? n : omp_get_max_threads();
@@ -408,13 +478,44 @@ double orc_residual_hat(const orc_clip* c, const orc_params* p, int t_ref, int p
   return residual_hat(fit, xhat, c->F + 2);
 }
 
+// Explicit Delta R for the plane theta[P] = (alpha, beta over D) regressed at
+// (t_ref, py, px), at frame t (new_window 0: eq. (7) over the last-event
+// window; 1: over frame t's window).  out[4] = (R, R_hat, weighted mean of the
+// translated residuals, compared change sign * sqrt(|R_hat - R|)).
+int orc_explicit(const orc_clip* c, const orc_params* p, int new_window, int t_ref, int t, int px,
+                 int py, const double* theta, double* out) {
+  if (!c || !p || !theta || !out || t_ref < 0 || t_ref >= c->T || t < 0 || t >= c->T || px < 0 ||
+      px >= c->W || py < 0 || py >= c->H)
+    return -2;
+  Clip cl{c};
+  const int D = c->F + 2;
+  std::vector<double> xc(D), xhat(D);
+  feature_vector(cl, p->r, t_ref, py, px, xc.data());
+  feature_vector(cl, p->r, t, py, px, xhat.data());
+  const WindowResiduals last = window_residuals(cl, p, t_ref, py, px, xc.data(), theta, xhat.data());
+  WindowResiduals cur = last;
+  if (new_window) cur = window_residuals(cl, p, t, py, px, xhat.data(), theta, xhat.data());
+  double dR = 0.0;
+  out[0] = last.R;
+  out[1] = cur.Rhat;
+  out[2] = cur.mean;
+  out[3] = explicit_change(cl, p, new_window, t_ref, t, py, px, theta, &dR);
+  return 0;
+}
+
 double orc_cond(const double* A, int P) {
   std::vector<double> M(A, A + static_cast<size_t>(P) * P);
   return jacobi_cond(M, P);
 }
 
 // Modes of orc_run.
-enum { ORC_THRESHOLDED = 0, ORC_EXHAUSTIVE = 1, ORC_RAW = 2 };
+enum {
+  ORC_THRESHOLDED = 0,
+  ORC_EXHAUSTIVE = 1,
+  ORC_RAW = 2,
+  ORC_EXPLICIT_LAST = 3,
+  ORC_EXPLICIT_NEW = 4
+};
 
 // Event simulation over a whole clip (or a subset of pixels).
 //
@@ -427,6 +528,11 @@ enum { ORC_THRESHOLDED = 0, ORC_EXHAUSTIVE = 1, ORC_RAW = 2 };
 //           explicitly and |R_hat - R - dL^2| is recorded.
 //   mode 1: WLR+ESIM: alpha_t for every pixel and frame, eq. (1) on alpha.
 //   mode 2: ESIM on the noisy frames: eq. (1) on y.
+//   mode 3: as mode 0 with Delta R = |R_hat - R| evaluated explicitly over
+//           the last-event window (eqs. (4) and (7)); fires when
+//           Delta R >= C^2, with the sign of the translated plane's mean
+//           residual.  dl receives sign * sqrt(Delta R).
+//   mode 4: as mode 3 with R_hat over the window of the current frame.
 //
 // pixels: optional list of pixel indices (ascending) to simulate; null = all.
 // Events are written in (t, py, px) order up to cap; the total count is
@@ -452,7 +558,9 @@ int64_t orc_run(const orc_clip* c, const orc_params* p, int mode, const int32_t*
   std::vector<double> theta_full;                           // only for identity check
   std::vector<double> Rref;
   std::vector<int32_t> tref(npix, 0);
-  if (check_identity && mode == ORC_THRESHOLDED) {
+  const bool explicit_mode = mode == ORC_EXPLICIT_LAST || mode == ORC_EXPLICIT_NEW;
+  const bool thresholded = mode == ORC_THRESHOLDED || explicit_mode;
+  if ((check_identity && mode == ORC_THRESHOLDED) || explicit_mode) {
     theta_full.assign(static_cast<size_t>(npix) * P, 0.0);
     Rref.assign(npix, 0.0);
   }
@@ -482,11 +590,23 @@ int64_t orc_run(const orc_clip* c, const orc_params* p, int mode, const int32_t*
       const int64_t pix = pix_of(k);
       const int py = static_cast<int>(pix / c->W), px = static_cast<int>(pix % c->W);
       fire[k] = 0;
-      if (mode == ORC_THRESHOLDED) {
+      if (thresholded) {
         if (t == 0) {
           Fit fit = regress(cl, p, 0, py, px, false, false);
           init_or_update(k, 0, fit);
           value[k] = NAN;
+          continue;
+        }
+        if (explicit_mode) {
+          double dR = 0.0;
+          const double v = explicit_change(cl, p, mode == ORC_EXPLICIT_NEW ? 1 : 0, tref[k], t, py, px,
+                                           &theta_full[k * P], &dR);
+          value[k] = v;
+          if (dR >= p->C * p->C) {
+            fire[k] = v > 0 ? 1 : -1;
+            Fit fit = regress(cl, p, t, py, px, false, false);
+            init_or_update(k, t, fit);
+          }
           continue;
         }
         double dlh = 0.0;
@@ -547,7 +667,7 @@ int64_t orc_run(const orc_clip* c, const orc_params* p, int mode, const int32_t*
   }
   for (int64_t k = 0; k < npix; ++k) {
     if (st_alpha) st_alpha[k] = ref[k];
-    if (mode == ORC_THRESHOLDED) {
+    if (thresholded) {
       for (int f = 0; f < F; ++f) {
         if (st_beta) st_beta[static_cast<int64_t>(f) * npix + k] = beta[k * F + f];
         if (st_xref) st_xref[static_cast<int64_t>(f) * npix + k] = xref[k * F + f];
