@@ -72,6 +72,26 @@ typedef enum {
                              Compiled for F in {7, 10}, lanes 4 and 16.        */
 } esim_precision;
 
+/* How the threshold of a thresholded conversion evaluates Delta R = |R_hat - R|
+ * (Sec. 2.2, eqs. (4), (7) and Prop. 1).  The two explicit forms are an
+ * ablation of the closed form; they need the state's bxy. */
+typedef enum {
+  ESIM_THRESHOLD_CLOSED = 0,      /* Prop. 1: Delta R = dL^2 with dL = beta_ref^T
+                                     (f_t - xref) over the F buffer channels
+                                     (default: the paper's method)            */
+  ESIM_THRESHOLD_LAST_WINDOW = 1, /* eq. (7) summed over the last-event window:
+                                     the samples, weights and centre of the
+                                     frame t_ref, the centre feature replaced
+                                     by frame t's; R of eq. (4) over the same
+                                     window for the stored plane.  Equal to the
+                                     closed form at the least-squares minimiser */
+  ESIM_THRESHOLD_NEW_WINDOW = 2   /* eq. (7) summed over frame t's window (its
+                                     samples, and weights of eq. (5) about
+                                     frame t's centre feature vector); R as
+                                     above.  Also sees brightness changes that
+                                     the features do not explain              */
+} esim_threshold;
+
 /* One clip.  y = log brightness [T][H][W] (see esim_log_brightness); feat =
  * the F feature buffers [T][F][H][W] in feat_dtype.  The image coordinates
  * are implicit features (px / r, py / r). */
@@ -102,6 +122,7 @@ typedef struct {
                               passed, and L_ref <- L_ref + n p C (n capped at
                               2^20 per pixel-frame).  Needs the state's `last`.
                               Ignored by the thresholded mode.                  */
+  int32_t threshold;       /* esim_threshold; the same for every clip of a plan  */
 } esim_params;
 
 /* Per-pixel reference state (Sec. 2.2: one regression model per pixel, kept
@@ -115,6 +136,12 @@ typedef struct {
   int32_t* tref;           /* [H*W]     frame of the last event                    */
   float* last;             /* [H*W]     compared value of the previous frame
                               (multi_crossing only; nullable otherwise)         */
+  float* bxy;              /* [2][H*W]  image-coordinate components of beta
+                              (x, then y) at the last event: the explicit
+                              thresholds need the whole plane.  Written, when
+                              non-NULL, by esim_events' model updates and by
+                              every step of a plan with an explicit threshold
+                              (the closed-form step leaves it untouched).     */
 } esim_state;
 
 /* Event sink.  Events are appended in (t, clip, py, px) order at *count (the
@@ -176,6 +203,14 @@ int esim_log_brightness(const float* E, float* y, int64_t n, float eps, void* st
  * 1 <= t < T, dL = sum_f beta_ref[f] (feat_t[f] - xref[f]) over the F buffer
  * channels (computed in FP64 from the FP32 state), written to dl[pixel offset
  * + p] (NaN for clips inactive at t); a pixel is flagged when dL^2 >= C^2.
+ * With an explicit esim_threshold, Delta R = |R_hat - R| is summed over the
+ * chosen window in FP64 from the stored plane (alpha, bxy, beta; FP32 weights
+ * as in the regression); a pixel is flagged when Delta R >= C^2, dl receives
+ * s * sqrt(Delta R) and s, the sign of the event, is the sign of the weighted
+ * mean of the translated plane's residuals y^i - alpha - beta^T (x^i - x_hat^c)
+ * (-1 when the mean is 0).  Over the last-event window s * sqrt(Delta R) is dL.
+ * The explicit forms need bxy and clips whose features stay below 4 GiB
+ * (E_UNSUPPORTED otherwise).
  * Flagged pixels are compacted into worklist as items (clip << 32 | p), in
  * ascending (clip, p) order.  count[0] = count[1] = flagged pixels (the work-list
  * length; a wave of the regression may straddle two clips).
@@ -213,12 +248,14 @@ int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const i
 
 /* Events and state updates (Sec. 1.1 eq. 1; Sec. 2.2; Sec. 3):
  *   ESIM_INIT:        every pixel of every clip active at t: state <- (alpha,
- *                     beta over the F buffer channels, feat_t, t) from dense
- *                     regression outputs (index pixel_offset(c) + p, stride
- *                     n_out).  No events.
+ *                     beta over the F buffer channels, feat_t, t; bxy from
+ *                     beta's coordinate rows when the state has bxy) from
+ *                     dense regression outputs (index pixel_offset(c) + p,
+ *                     stride n_out).  No events.
  *   ESIM_THRESHOLDED: for the work-list items of a threshold call at t: emit
  *                     (px, py, t, sign dl) and replace the state with the
- *                     item's regression (alpha[i], beta[.., i]), feat_t and t.
+ *                     item's regression (alpha[i], beta[.., i], bxy as for
+ *                     INIT), feat_t and t.
  *   ESIM_EXHAUSTIVE:  every pixel: d = alpha - state.alpha (L_ref); if
  *                     |d| >= C emit sign d and set L_ref <- alpha.  At t = 0
  *                     (or for a fresh state) call ESIM_INIT first.
@@ -239,7 +276,9 @@ int esim_events(esim_plan plan, int32_t t, int32_t mode, const int64_t* worklist
  *   ESIM_THRESHOLDED: threshold (Prop. 1) at t >= 1, append the flagged
  *                     pixels' events (sign of dL, during the compaction), and
  *                     regress the flagged pixels, each regression writing its
- *                     model straight into the state.
+ *                     model straight into the state.  With an explicit
+ *                     esim_threshold the models pass through the plan's
+ *                     buffers (one more launch), so that bxy is written too.
  *   ESIM_EXHAUSTIVE:  regress every pixel, then eq. (1) on alpha (as
  *                     esim_events).
  *   ESIM_RAW:         eq. (1) on y_t.

@@ -23,6 +23,7 @@ OK, E_INVAL, E_HIP, E_CAPACITY, E_UNSUPPORTED = 0, -1, -2, -3, -4
 F32, F16 = 0, 1
 INIT, THRESHOLDED, EXHAUSTIVE, RAW = 0, 1, 2, 3
 GRAM_F64, GRAM_F32C = 0, 1
+THRESHOLD_CLOSED, THRESHOLD_LAST_WINDOW, THRESHOLD_NEW_WINDOW = 0, 1, 2
 
 
 class EsimError(RuntimeError):
@@ -41,12 +42,14 @@ class esim_params(ctypes.Structure):
     _fields_ = [("r", ctypes.c_int32), ("tr", ctypes.c_int32), ("C", ctypes.c_double),
                 ("h", ctypes.c_double), ("b", ctypes.c_double * MAX_D),
                 ("ridge", ctypes.c_double), ("precision", ctypes.c_int32),
-                ("kappa_fp64", ctypes.c_double), ("multi_crossing", ctypes.c_int32)]
+                ("kappa_fp64", ctypes.c_double), ("multi_crossing", ctypes.c_int32),
+                ("threshold", ctypes.c_int32)]
 
 
 class esim_state(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p),
-                ("xref", ctypes.c_void_p), ("tref", ctypes.c_void_p), ("last", ctypes.c_void_p)]
+                ("xref", ctypes.c_void_p), ("tref", ctypes.c_void_p), ("last", ctypes.c_void_p),
+                ("bxy", ctypes.c_void_p)]
 
 
 class esim_events_buf(ctypes.Structure):
@@ -125,11 +128,13 @@ class Params:
 
     def __init__(self, r: int, tr: int, C: float, h: float = 1.0,
                  b: Optional[Sequence[float]] = None, ridge: float = 1e-6,
-                 precision: int = GRAM_F64, kappa_fp64: float = 1e6, multi_crossing: bool = False):
+                 precision: int = GRAM_F64, kappa_fp64: float = 1e6, multi_crossing: bool = False,
+                 threshold: int = THRESHOLD_CLOSED):
         self.r, self.tr, self.C, self.h = int(r), int(tr), float(C), float(h)
         self.b = None if b is None else [float(v) for v in b]
         self.ridge, self.precision, self.kappa_fp64 = float(ridge), int(precision), float(kappa_fp64)
         self.multi_crossing = bool(multi_crossing)
+        self.threshold = int(threshold)
 
     def struct(self, F: int) -> esim_params:
         b = [1.0] * (F + 2) if self.b is None else list(self.b)
@@ -137,7 +142,7 @@ class Params:
             raise ValueError(f"b needs F+2 = {F + 2} values")
         arr = (ctypes.c_double * MAX_D)(*(b + [1.0] * (MAX_D - len(b))))
         return esim_params(self.r, self.tr, self.C, self.h, arr, self.ridge, self.precision,
-                           self.kappa_fp64, int(self.multi_crossing))
+                           self.kappa_fp64, int(self.multi_crossing), self.threshold)
 
 
 class State:
@@ -150,10 +155,11 @@ class State:
         self.xref = torch.zeros((F, HW), dtype=torch.float32, device=device)
         self.tref = torch.zeros(HW, dtype=torch.int32, device=device)
         self.last = torch.zeros(HW, dtype=torch.float32, device=device)
+        self.bxy = torch.zeros((2, HW), dtype=torch.float32, device=device)
 
     def struct(self) -> esim_state:
         return esim_state(_ptr(self.alpha), _ptr(self.beta), _ptr(self.xref), _ptr(self.tref),
-                          _ptr(self.last))
+                          _ptr(self.last), _ptr(self.bxy))
 
 
 class Plan:

@@ -16,7 +16,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libesim.so")
-SOURCES = ["esim_api.hip", "esim_compact.hip", "esim_regress.hip", "esim_backward.hip", "esim_metrics.hip"]
+SOURCES = ["esim_api.hip", "esim_compact.hip", "esim_regress.hip", "esim_backward.hip", "esim_metrics.hip",
+           "esim_explicit.hip"]
 # the regression kernels of feature count f are compiled from esim_regress_inst.hip
 # with -DESIM_REGRESS_F=f, one object each, so that they build in parallel
 REGRESS_F = range(1, 13)

@@ -33,6 +33,8 @@ struct esim_plan_s {
   int64_t* step_wl = nullptr;     // [wl_capacity]
   int32_t* step_count = nullptr;  // [2]
   float* step_alpha = nullptr;    // [npix]
+  float* step_beta = nullptr;     // [F + 2][npix] (explicit thresholds only)
+  int thr = ESIM_THRESHOLD_CLOSED;
 };
 
 namespace {
@@ -98,7 +100,40 @@ bool multi_state_ok(esim_plan pl) {
 bool full_state(esim_plan pl) {
   for (const auto& c : pl->host)
     if (!c.st_beta || !c.st_xref || !c.st_alpha || !c.st_tref) return false;
+  if (pl->thr != ESIM_THRESHOLD_CLOSED)
+    for (const auto& c : pl->host)
+      if (!c.st_bxy) return false;
   return true;
+}
+
+// The explicit thresholds address every frame of a clip through one buffer
+// resource (32-bit offsets).
+int explicit_ok(esim_plan pl) {
+  if (pl->thr == ESIM_THRESHOLD_CLOSED) return ok();
+  for (const auto& c : pl->host)
+    if (!c.st_bxy) return fail(ESIM_E_INVAL, "explicit thresholds need the state's bxy");
+  if (pl->max_feat_bytes >= (1ull << 32))
+    return fail(ESIM_E_UNSUPPORTED, "explicit thresholds need feature arrays below 4 GiB");
+  return ok();
+}
+
+// Threshold at t into the plan's workspace, then the compaction (work list,
+// count and, with ev, the flagged pixels' events).
+int threshold_compact(esim_plan pl, int32_t t, float* dl, int64_t* worklist, int32_t* count,
+                      const esim::EventsDev* ev, hipStream_t s) {
+  if (pl->thr == ESIM_THRESHOLD_CLOSED)
+    return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold, dl,
+                                               nullptr, pl->ws, worklist, count, ev, s),
+                     "threshold");
+  int rc = explicit_ok(pl);
+  if (rc != ESIM_OK) return rc;
+  rc = hip_check(esim::launch_explicit_flag(pl->dev, pl->nclips, pl->nblk, t, pl->F, pl->f16, dl, pl->ws,
+                                            ev ? ev->count : nullptr, s),
+                 "threshold(explicit)");
+  if (rc != ESIM_OK) return rc;
+  return hip_check(esim::launch_scatter(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold, nullptr,
+                                        pl->ws, worklist, count, ev, s),
+                   "threshold(compaction)");
 }
 
 }  // namespace
@@ -173,6 +208,14 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
         delete pl;
         return fail(ESIM_E_UNSUPPORTED, "all clips of a plan share the precision");
       }
+      if (p.threshold < ESIM_THRESHOLD_CLOSED || p.threshold > ESIM_THRESHOLD_NEW_WINDOW) {
+        delete pl;
+        return fail(ESIM_E_INVAL, "bad threshold");
+      }
+      if (c > 0 && p.threshold != params[0].threshold) {
+        delete pl;
+        return fail(ESIM_E_UNSUPPORTED, "all clips of a plan share the threshold form");
+      }
       for (int d = 0; d < k.F + 2; ++d)
         if (!(p.b[d] > 0) || std::isinf(p.b[d])) {
           delete pl;
@@ -187,7 +230,9 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
         cd.st_xref = states[c].xref;
         cd.st_tref = states[c].tref;
         cd.st_last = states[c].last;
+        cd.st_bxy = states[c].bxy;
       }
+      cd.thr = p.threshold;
       cd.W = k.W;
       cd.H = k.H;
       cd.T = k.T;
@@ -234,6 +279,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     }
     // the compensated-FP32 instances exist for 4 and 16 lanes only
     if (params[0].precision == ESIM_GRAM_F32C) pl->lanes_dense = 4;
+    pl->thr = params[0].threshold;
     pl->npix = pix;
     pl->nblk = blk;
     pl->wl_capacity = wl;
@@ -320,6 +366,8 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       so = align(so + sizeof(int32_t) * 2);
       const size_t s_al = so;
       so = align(so + sizeof(float) * pix);
+      const size_t s_be = so;
+      if (pl->thr != ESIM_THRESHOLD_CLOSED) so = align(so + sizeof(float) * (pl->F + 2) * pix);
       e = hipMalloc(&pl->step_mem, so);
       if (e != hipSuccess) {
         hipFree(pl->ws_mem);
@@ -330,6 +378,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       pl->step_wl = reinterpret_cast<int64_t*>(sm + s_wl);
       pl->step_count = reinterpret_cast<int32_t*>(sm + s_cnt);
       pl->step_alpha = reinterpret_cast<float*>(sm + s_al);
+      if (pl->thr != ESIM_THRESHOLD_CLOSED) pl->step_beta = reinterpret_cast<float*>(sm + s_be);
     }
     *out = pl;
     return ok();
@@ -374,10 +423,7 @@ int esim_wlr_threshold(esim_plan pl, int32_t t, float* dl, int64_t* worklist, in
     for (const auto& c : pl->host)
       if (!c.st_beta || !c.st_xref || !c.st_alpha || !c.st_tref)
         return fail(ESIM_E_INVAL, "threshold needs the full state (alpha, beta, xref, tref)");
-    return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold,
-                                               dl, nullptr, pl->ws, worklist, count, nullptr,
-                                               static_cast<hipStream_t>(stream)),
-                     "threshold");
+    return threshold_compact(pl, t, dl, worklist, count, nullptr, static_cast<hipStream_t>(stream));
   } catch (...) {
     return fail(ESIM_E_HIP, "exception");
   }
@@ -454,20 +500,34 @@ int esim_step(esim_plan pl, int32_t t, int32_t mode, float* dl, esim_events_buf*
       for (const auto& c : pl->host)
         if (!c.st_alpha) return fail(ESIM_E_INVAL, "state alpha is null");
     }
-    if (mode == ESIM_INIT)
-      return launch_plan_regress(pl, t, nullptr, nullptr, pl->npix, nullptr, nullptr, nullptr, nullptr,
-                                 true, s);
+    if (mode == ESIM_INIT) {
+      if (pl->thr == ESIM_THRESHOLD_CLOSED)
+        return launch_plan_regress(pl, t, nullptr, nullptr, pl->npix, nullptr, nullptr, nullptr, nullptr,
+                                   true, s);
+      // explicit thresholds keep the whole plane: through the plan's buffers
+      int rc = launch_plan_regress(pl, t, nullptr, nullptr, pl->npix, pl->step_alpha, pl->step_beta, nullptr,
+                                   nullptr, false, s);
+      if (rc != ESIM_OK) return rc;
+      return hip_check(esim::launch_init(pl->dev, pl->nclips, pl->nblk, t, pl->step_alpha, pl->step_beta,
+                                         pl->npix, s),
+                       "step(init)");
+    }
     if (!ev || !ev->x || !ev->y || !ev->t || !ev->p || !ev->count || ev->capacity < 0)
       return fail(ESIM_E_INVAL, "events buffer incomplete");
     esim::EventsDev ed{ev->x, ev->y, ev->t, ev->p, ev->clip, ev->capacity, ev->count, ev->ts};
     if (mode == ESIM_THRESHOLDED) {
-      int rc = hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold,
-                                                   dl, nullptr, pl->ws, pl->step_wl,
-                                                   pl->step_count, &ed, s),
-                         "step(threshold)");
+      int rc = threshold_compact(pl, t, dl, pl->step_wl, pl->step_count, &ed, s);
       if (rc != ESIM_OK) return rc;
-      return launch_plan_regress(pl, t, pl->step_wl, pl->step_count, pl->wl_capacity, nullptr, nullptr,
-                                 nullptr, nullptr, true, s);
+      if (pl->thr == ESIM_THRESHOLD_CLOSED)
+        return launch_plan_regress(pl, t, pl->step_wl, pl->step_count, pl->wl_capacity, nullptr, nullptr,
+                                   nullptr, nullptr, true, s);
+      rc = launch_plan_regress(pl, t, pl->step_wl, pl->step_count, pl->wl_capacity, pl->step_alpha,
+                               pl->step_beta, nullptr, nullptr, false, s);
+      if (rc != ESIM_OK) return rc;
+      return hip_check(esim::launch_list_state(pl->dev, pl->nclips, t, pl->step_wl, pl->step_count,
+                                               pl->wl_capacity, pl->step_alpha, pl->step_beta,
+                                               pl->wl_capacity, s),
+                       "step(state)");
     }
     if ((mode == ESIM_EXHAUSTIVE || mode == ESIM_RAW) && !multi_state_ok(pl))
       return fail(ESIM_E_INVAL, "multi_crossing needs the state's last");

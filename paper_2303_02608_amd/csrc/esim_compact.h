@@ -7,6 +7,14 @@ namespace esim {
 
 enum { kFlagThreshold = 0, kFlagExhaustive = 1, kFlagRaw = 2 };
 
+// Clip of kBlock-pixel block b of a flag/scatter grid.
+__device__ __forceinline__ int block_clip(const ClipDev* clips, int nclips, int64_t b) {
+  int cl = 0;
+  for (int c = 1; c < nclips; ++c)
+    if (clips[c].blk_off <= b) cl = c;
+  return cl;
+}
+
 // Device view of an esim_events_buf.
 struct EventsDev {
   int32_t* x;
@@ -33,6 +41,18 @@ constexpr int64_t kDirectPrefixBlocks = 4096;
 hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
                                float* dl, const float* alpha, const Workspace& ws, int64_t* worklist,
                                int32_t* count, const EventsDev* ev, hipStream_t s);
+
+// The compaction after a flag kernel that has already filled ws (chunk totals
+// when needed, then the scatter), as in launch_flag_compact.
+hipError_t launch_scatter(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
+                          const float* alpha, const Workspace& ws, int64_t* worklist, int32_t* count,
+                          const EventsDev* ev, hipStream_t s);
+
+// State <- the models of the work-list items (alpha[i], beta[.., i]), feat_t
+// and t, without events (the step's explicit-threshold path).
+hipError_t launch_list_state(const ClipDev* clips, int nclips, int t, const int64_t* worklist,
+                             const int32_t* count, int64_t max_items, const float* alpha,
+                             const float* beta, int64_t n_out, hipStream_t s);
 
 hipError_t launch_list_events(const ClipDev* clips, int nclips, int t, const int64_t* worklist,
                               const int32_t* count, int64_t max_items, const float* dl,

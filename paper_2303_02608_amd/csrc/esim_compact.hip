@@ -30,13 +30,6 @@
 namespace esim {
 namespace {
 
-__device__ __forceinline__ int block_clip(const ClipDev* clips, int nclips, int64_t b) {
-  int cl = 0;
-  for (int c = 1; c < nclips; ++c)
-    if (clips[c].blk_off <= b) cl = c;
-  return cl;
-}
-
 __global__ void __launch_bounds__(256) log_kernel(const float* __restrict__ E, float* __restrict__ y,
                                                   int64_t n, float eps) {
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -250,6 +243,23 @@ scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, W
   }
 }
 
+// The model of regression output i (alpha[i], beta[d * n_out + i] over D,
+// coordinates first) becomes pixel p's reference state at frame t.
+__device__ __forceinline__ void store_model(const ClipDev& C, int64_t p, int t, int64_t i,
+                                            const float* __restrict__ alpha,
+                                            const float* __restrict__ beta, int64_t n_out) {
+  C.st_alpha[p] = alpha[i];
+  if (beta && C.st_beta)
+    for (int f = 0; f < C.F; ++f) C.st_beta[f * C.HW + p] = beta[(2 + f) * n_out + i];
+  if (beta && C.st_bxy) {
+    C.st_bxy[p] = beta[i];
+    C.st_bxy[C.HW + p] = beta[n_out + i];
+  }
+  if (C.st_xref)
+    for (int f = 0; f < C.F; ++f) C.st_xref[f * C.HW + p] = feat_value(C, t, f, p);
+  if (C.st_tref) C.st_tref[p] = t;
+}
+
 __device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, int t,
                                  const int64_t* __restrict__ worklist, int64_t n, int64_t base,
                                  int64_t stride, const float* __restrict__ dl,
@@ -297,12 +307,26 @@ __device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, 
       if (ev.clip) ev.clip[e] = cl;
       if (ev.ts) ev.ts[e] = static_cast<float>(t);
     }
-    C.st_alpha[p] = alpha[i];
-    for (int f = 0; f < C.F; ++f) {
-      C.st_beta[f * C.HW + p] = beta[(2 + f) * n_out + i];
-      C.st_xref[f * C.HW + p] = feat_value(C, t, f, p);
-    }
-    C.st_tref[p] = t;
+    store_model(C, p, t, i, alpha, beta, n_out);
+  }
+}
+
+__global__ void __launch_bounds__(256)
+list_state_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const int64_t* __restrict__ worklist,
+                  const int32_t* __restrict__ count, const float* __restrict__ alpha,
+                  const float* __restrict__ beta, int64_t n_out, int64_t max_items) {
+  const int64_t n = max(static_cast<int64_t>(0),
+                        min(static_cast<int64_t>(count[0]), min(max_items, n_out)));
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride) {
+    const int64_t it = worklist[i];
+    if (it < 0) continue;
+    const int cl = static_cast<int>((it >> 32) & 0xFFF);
+    if (cl >= nclips) continue;
+    const ClipDev& C = clips[cl];
+    const int64_t p = it & 0xFFFFFFFFll;
+    if (p >= C.HW || t >= C.T) continue;
+    store_model(C, p, t, i, alpha, beta, n_out);
   }
 }
 
@@ -318,13 +342,7 @@ init_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const float* _
     C.st_alpha[p] = C.y[static_cast<int64_t>(t) * C.HW + p];
     return;
   }
-  const int64_t i = C.pix_off + p;
-  C.st_alpha[p] = alpha[i];
-  if (beta && C.st_beta)
-    for (int f = 0; f < C.F; ++f) C.st_beta[f * C.HW + p] = beta[(2 + f) * n_out + i];
-  if (C.st_xref)
-    for (int f = 0; f < C.F; ++f) C.st_xref[f * C.HW + p] = feat_value(C, t, f, p);
-  if (C.st_tref) C.st_tref[p] = t;
+  store_model(C, p, t, C.pix_off + p, alpha, beta, n_out);
 }
 
 }  // namespace
@@ -343,6 +361,13 @@ hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, i
   int64_t* wl = mode == kFlagThreshold ? worklist : nullptr;
   hipLaunchKernelGGL(flag_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
                      t, mode, dl, alpha, ws, ev ? ev->count : nullptr);
+  return launch_scatter(clips, nclips, nblk, t, mode, alpha, ws, wl, count, ev, s);
+}
+
+hipError_t launch_scatter(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
+                          const float* alpha, const Workspace& ws, int64_t* worklist, int32_t* count,
+                          const EventsDev* ev, hipStream_t s) {
+  int64_t* wl = mode == kFlagThreshold ? worklist : nullptr;
   const int chunked = nblk > kDirectPrefixBlocks ? 1 : 0;
   if (chunked)
     hipLaunchKernelGGL(chunk_kernel, dim3(static_cast<unsigned>((nblk + kChunkBlocks - 1) / kChunkBlocks)),
@@ -363,6 +388,17 @@ hipError_t launch_list_events(const ClipDev* clips, int nclips, int t, const int
   hipLaunchKernelGGL(list_events_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, clips,
                      nclips, t, worklist, count, dl, alpha, beta, n_out, max_items, ws, ev);
   hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, s, ev.count, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_list_state(const ClipDev* clips, int nclips, int t, const int64_t* worklist,
+                             const int32_t* count, int64_t max_items, const float* alpha,
+                             const float* beta, int64_t n_out, hipStream_t s) {
+  int64_t blocks = (max_items + 255) / 256;
+  if (blocks > 512) blocks = 512;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(list_state_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, clips, nclips,
+                     t, worklist, count, alpha, beta, n_out, max_items);
   return hipGetLastError();
 }
 

@@ -35,6 +35,8 @@ struct ClipDev {
   double c2[ESIM_MAX_D];   // 1 / (h b_j)^2
   double sf[ESIM_MAX_D];   // 1 / (h b_j)
   double gbk[ESIM_MAX_D];  // 1 / (h^2 b_j^3)
+  float* st_bxy;           // [2][HW] coordinate components of beta (nullable)
+  int32_t thr;             // esim_threshold
 };
 
 // Compaction workspace of a plan (device).
@@ -198,5 +200,11 @@ struct NnArgs {
 };
 size_t nn_scratch_bytes(int W, int H, int T);
 hipError_t launch_nn(const NnArgs& a, hipStream_t s);
+
+// Explicit Delta R threshold (dense over the plan's pixels at frame t): fills
+// dl and the flag/polarity ballots and block counts of the compaction
+// workspace, like the closed-form flag kernel.
+hipError_t launch_explicit_flag(const ClipDev* clips, int nclips, int64_t nblk, int t, int F, bool f16,
+                                float* dl, const Workspace& ws, const int64_t* ev_count, hipStream_t s);
 
 }  // namespace esim

@@ -77,9 +77,15 @@ def test_bad_shapes_and_params_are_rejected(lib):
     for p in (B.Params(r=0, tr=0, C=0.2), B.Params(r=5, tr=-1, C=0.2), B.Params(r=5, tr=0, C=0.0),
               B.Params(r=5, tr=0, C=0.2, h=0.0), B.Params(r=5, tr=0, C=0.2, ridge=-1.0),
               B.Params(r=5, tr=0, C=0.2, b=[1.0] * 8 + [0.0]),
-              B.Params(r=5, tr=0, C=0.2, precision=7)):
+              B.Params(r=5, tr=0, C=0.2, precision=7), B.Params(r=5, tr=0, C=0.2, threshold=3),
+              B.Params(r=5, tr=0, C=0.2, threshold=-1)):
         assert create(clip, p.struct(F)) == B.E_INVAL, vars(p)
     # mixed F across clips of one plan
     clips = (B.esim_clip * 2)(clip, B.esim_clip(64, 64, 4, 3, B.F32, 1, 1))
     pars = (B.esim_params * 2)(good.struct(F), good.struct(F))
+    assert lib.esim_plan_create(clips, pars, None, 2, ctypes.byref(out)) == B.E_UNSUPPORTED
+    # the threshold form is one per plan
+    pars = (B.esim_params * 2)(good.struct(F),
+                               B.Params(r=5, tr=0, C=0.2, threshold=B.THRESHOLD_NEW_WINDOW).struct(F))
+    clips = (B.esim_clip * 2)(clip, clip)
     assert lib.esim_plan_create(clips, pars, None, 2, ctypes.byref(out)) == B.E_UNSUPPORTED
