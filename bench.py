@@ -21,7 +21,10 @@ about 2e8 pixel-frames: one batched plan against the clips converted one by
 one) and `diff` (640x480x60: forward regressions of the differentiation loss
 and their adjoint), `quality` (events of the three conversions against ESIM on
 the noise-free frames: precision, recall, F1 and Chamfer distance over a sweep
-of C, with the conversion times).
+of C, with the conversion times), `threshold` (the closed form of Prop. 1
+against the explicit Delta R sums over the last-event window and over the
+current frame's window: times, events and quality, on the clip and under a
+global illumination flicker).
 
 Roofline: the dominant kernel is the regression.  Its launches are bracketed
 with HIP events on the launch stream during an instrumented eager pass of the
@@ -285,6 +288,123 @@ def workload_quality(args, B, synth, Simulator):
             "taus": taus, "rmax": rmax, "sweep": rows}
 
 
+def window_sum_flops(om, F):
+    """Algorithmic FLOPs of one window pass of the explicit thresholds (W,
+    sum w r, sum w r^2 of a stored plane), per window sample: the eq. (5)
+    exponent over the D regressors (2F scaled feature offsets, 2D squares),
+    the plane's residual (2D + 1) and the sums (5)."""
+    D = F + 2
+    return om.astype(np.float64) * (2 * F + 4 * D + 6)
+
+
+def workload_threshold(args, B, synth, Simulator):
+    """The three threshold forms of Sec. 2.2 on the DVS clip: the closed form
+    of Prop. 1 and the explicit sums of eq. (7) over the last-event window and
+    over the current frame's window.  Per form: conversion time, flagged
+    pixels, events and their quality against ESIM on the noise-free frames, on
+    the clip as generated and with a global illumination flicker (a gain on
+    every pixel, the features unchanged) applied to both; plus the explicit
+    threshold launches timed with HIP events on their stream."""
+    import torch
+    from paper_2303_02608_amd import quality as Q
+    cfg = synth.config_spec(1)
+    spec = cfg["spec"]
+    t0 = time.time()
+    d = synth.make_clip(spec, device="cuda", reference=True)
+    feat = d["feat"]
+    T, F, H, W = feat.shape
+    HW = H * W
+    r, tr, C = cfg["r"], cfg["tr"], cfg["C"]
+    log(f"generated {W}x{H}x{T} with reference frames in {time.time() - t0:.1f}s")
+    taus, rmax = [5e-4, 2e-3, 5e-3, 1e-2], 0.05
+    tt = torch.arange(T, device="cuda", dtype=torch.float32)
+    gain = torch.exp(0.3 * torch.sin(2 * np.pi * tt / 40.0))[:, None, None]
+    scenes = {"as_generated": (d["E"], d["E_ref"]), "flicker": (d["E"] * gain, d["E_ref"] * gain)}
+    xs, ys = np.arange(HW) % W, np.arange(HW) // W
+    forms = (("closed", B.THRESHOLD_CLOSED), ("last_window", B.THRESHOLD_LAST_WINDOW),
+             ("new_window", B.THRESHOLD_NEW_WINDOW))
+    out = {"workload": f"threshold forms, DVS {W}x{H}x{T}, F={F} f32, r={r}, tr={tr}, C={C}; "
+                       f"reference = ESIM on the noise-free frames; flicker = gain "
+                       f"exp(0.3 sin(2 pi t / 40)) on every pixel",
+           "taus": taus, "rmax": rmax}
+    stream = torch.cuda.current_stream()
+    for sname, (E, Eref) in scenes.items():
+        y = B.log_brightness(E.contiguous())
+        yref = B.log_brightness(Eref.contiguous())
+        p0 = B.Params(r=r, tr=tr, C=C)
+        refd = Q.to_device(Simulator(yref, feat, p0).run("raw"))
+        rows = {}
+        for name, thr in forms:
+            p = B.Params(r=r, tr=tr, C=C, threshold=thr)
+            sim = Simulator(y, feat, p)
+            run = _graph(lambda s=sim: s.enqueue("thresholded"))
+            ms = _time_ms(run, max(1, args.steps))
+            ev = sim.events()
+            m = Q.metrics(Q.to_device(ev), refd, W, H, T, taus, rmax)
+            row = {"ms": round(ms, 3), "pixel_frames_per_s": round(T * HW / (ms * 1e-3), 1),
+                   "events": ev["count"], "flagged_fraction": round(ev["count"] / ((T - 1) * HW), 5),
+                   "P": [round(v, 4) for v in m["P"]], "R": [round(v, 4) for v in m["R"]],
+                   "F": [round(v, 4) for v in m["F"]], "CD": m["CD"]}
+            if thr != B.THRESHOLD_CLOSED and sname == "as_generated":
+                # separate calls: the threshold launch (explicit kernel + compaction) and the
+                # event call (events, state update and the window sums of the new planes)
+                plan = sim.plan
+                sim.ev.count.zero_()
+                B.regress(plan, 0, None, None, HW, sim.alpha, sim.beta)
+                B.events(plan, 0, B.INIT, None, alpha=sim.alpha, beta=sim.beta, n_out=HW)
+                th_marks, ev_marks = [], []
+                for t in range(1, T):
+                    marks = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+                    marks[0].record(stream)
+                    B.threshold(plan, t, sim.dl, sim.worklist, sim.count)
+                    marks[1].record(stream)
+                    B.regress(plan, t, sim.worklist, sim.count, HW, sim.alpha, sim.beta)
+                    marks[2].record(stream)
+                    B.events(plan, t, B.THRESHOLDED, sim.ev, worklist=sim.worklist, count=sim.count,
+                             dl=sim.dl, alpha=sim.alpha, beta=sim.beta, n_out=HW)
+                    marks[3].record(stream)
+                    th_marks.append((marks[0], marks[1]))
+                    ev_marks.append((marks[2], marks[3]))
+                torch.cuda.synchronize()
+                th_ms = np.array([a.elapsed_time(b) for a, b in th_marks])
+                ev_ms = np.array([a.elapsed_time(b) for a, b in ev_marks])
+                upd = sim.events()
+                om_upd = omega_sizes(upd["x"].astype(np.int64), upd["y"].astype(np.int64),
+                                     upd["t"].astype(np.int64), W, H, T, r, tr)
+                fl_upd = window_sum_flops(om_upd, F).sum()
+                if thr == B.THRESHOLD_LAST_WINDOW:
+                    # state beta, xref, rmom and the frame's features read, dl written
+                    nbytes = HW * ((3 * F + 2) * 4 + 4)
+                    ach = nbytes / (th_ms.mean() * 1e-3) / 1e9
+                    roofl = {"bound": "hbm", "achieved": round(ach, 1), "peak": PEAK_HBM_GBS,
+                             "unit": "GB/s", "frac": round(ach / PEAK_HBM_GBS, 4),
+                             "bytes_per_launch": nbytes}
+                else:
+                    fl = sum(window_sum_flops(omega_sizes(xs, ys, np.full(HW, t), W, H, T, r, tr),
+                                              F).sum() for t in range(1, T))
+                    ach = fl / (th_ms.sum() * 1e-3) / 1e12
+                    roofl = {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_ALU_TFLOPS,
+                             "unit": "TFLOP/s", "frac": round(ach / PEAK_ALU_TFLOPS, 4),
+                             "flop_per_launch": float(fl / th_ms.size)}
+                form = "new" if thr == B.THRESHOLD_NEW_WINDOW else "last"
+                row["threshold_launch"] = {
+                    "kernel": f"explicit_flag_kernel<F={F},f32,{form}> + compaction",
+                    "launches": int(th_ms.size), "avg_ms": round(float(th_ms.mean()), 4),
+                    "roofline": roofl, "share_of_conversion": round(float(th_ms.sum()) / ms, 3)}
+                row["update_launch"] = {
+                    "kernels": "events + state update + moments_kernel (16 lanes per item)",
+                    "launches": int(ev_ms.size), "avg_ms": round(float(ev_ms.mean()), 4),
+                    "window_sum_tflops": round(fl_upd / (ev_ms.sum() * 1e-3) / 1e12, 3),
+                    "share_of_conversion": round(float(ev_ms.sum()) / ms, 3)}
+                log(f"{name}: threshold launches avg {th_ms.mean():.4f} ms ({roofl['frac']:.3f} of peak), "
+                    f"event calls avg {ev_ms.mean():.4f} ms")
+            rows[name] = row
+            log(f"{sname} {name}: {ms:.2f} ms, {ev['count']} events, F {row['F']}")
+            del sim, run
+        out[sname] = rows
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -302,7 +422,8 @@ def main():
                     help="load the clip saved by --save-clip instead of generating it")
     ap.add_argument("--schedule", type=str, default=None,
                     help="lanes_dense,lanes_list,blocks_per_cu (skips the autotuner)")
-    ap.add_argument("--workload", choices=("dvs", "precision", "batch", "diff", "quality"), default="dvs",
+    ap.add_argument("--workload", choices=("dvs", "precision", "batch", "diff", "quality", "threshold"),
+                    default="dvs",
                     help="dvs (default, the contract line) or one of the extension workloads")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (the "
@@ -329,7 +450,7 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload != "dvs":
         fn = {"precision": workload_precision, "batch": workload_batch, "diff": workload_diff,
-              "quality": workload_quality}
+              "quality": workload_quality, "threshold": workload_threshold}
         res = fn[args.workload](args, B, synth, Simulator)
         res = {"metric": f"{args.workload} workload", "n_gpus": 1, "dtype": "f64",
                "data": "synthetic", **res}

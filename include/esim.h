@@ -142,6 +142,11 @@ typedef struct {
                               non-NULL, by esim_events' model updates and by
                               every step of a plan with an explicit threshold
                               (the closed-form step leaves it untouched).     */
+  float* rmom;             /* [2][H*W]  window sums of the stored plane over its
+                              own (last-event) window, taken when the model is
+                              stored: R of eq. (4), then the weighted mean
+                              residual m1 = sum w r / W.  Explicit thresholds
+                              only (nullable otherwise).                       */
 } esim_state;
 
 /* Event sink.  Events are appended in (t, clip, py, px) order at *count (the
@@ -203,14 +208,19 @@ int esim_log_brightness(const float* E, float* y, int64_t n, float eps, void* st
  * 1 <= t < T, dL = sum_f beta_ref[f] (feat_t[f] - xref[f]) over the F buffer
  * channels (computed in FP64 from the FP32 state), written to dl[pixel offset
  * + p] (NaN for clips inactive at t); a pixel is flagged when dL^2 >= C^2.
- * With an explicit esim_threshold, Delta R = |R_hat - R| is summed over the
- * chosen window in FP64 from the stored plane (alpha, bxy, beta; FP32 weights
- * as in the regression); a pixel is flagged when Delta R >= C^2, dl receives
- * s * sqrt(Delta R) and s, the sign of the event, is the sign of the weighted
- * mean of the translated plane's residuals y^i - alpha - beta^T (x^i - x_hat^c)
- * (-1 when the mean is 0).  Over the last-event window s * sqrt(Delta R) is dL.
- * The explicit forms need bxy and clips whose features stay below 4 GiB
- * (E_UNSUPPORTED otherwise).
+ * With an explicit esim_threshold, Delta R = |R_hat - R| comes from window sums
+ * of the stored plane (alpha, bxy, beta) in FP64 with FP32 weights as in the
+ * regression.  R and m1 are the state's rmom.  Over the last-event window the
+ * samples are those of t_ref and only the centre moves, so the translated
+ * residuals are r_i + d with d = beta^T (x_hat^c - x^c) and eq. (7) expands
+ * exactly: R_hat = R + 2 d m1 + d^2, mean m1 + d.  Over frame t's window
+ * R_hat and the mean are summed at frame t.  A pixel is flagged when
+ * Delta R >= C^2; dl receives s * sqrt(Delta R), s (the sign of the event)
+ * being the sign of the weighted mean of the translated plane's residuals
+ * y^i - alpha - beta^T (x^i - x_hat^c) (-1 when the mean is 0).  Over the
+ * last-event window s * sqrt(Delta R) is dL up to the m1 term (zero at the
+ * least-squares minimiser).  The explicit forms need bxy, rmom and clips
+ * whose features stay below 4 GiB (E_UNSUPPORTED otherwise).
  * Flagged pixels are compacted into worklist as items (clip << 32 | p), in
  * ascending (clip, p) order.  count[0] = count[1] = flagged pixels (the work-list
  * length; a wave of the regression may straddle two clips).
@@ -251,11 +261,12 @@ int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const i
  *                     beta over the F buffer channels, feat_t, t; bxy from
  *                     beta's coordinate rows when the state has bxy) from
  *                     dense regression outputs (index pixel_offset(c) + p,
- *                     stride n_out).  No events.
+ *                     stride n_out).  No events.  Plans with an explicit
+ *                     threshold then sum rmom over each stored plane's window.
  *   ESIM_THRESHOLDED: for the work-list items of a threshold call at t: emit
  *                     (px, py, t, sign dl) and replace the state with the
- *                     item's regression (alpha[i], beta[.., i], bxy as for
- *                     INIT), feat_t and t.
+ *                     item's regression (alpha[i], beta[.., i], bxy and rmom
+ *                     as for INIT), feat_t and t.
  *   ESIM_EXHAUSTIVE:  every pixel: d = alpha - state.alpha (L_ref); if
  *                     |d| >= C emit sign d and set L_ref <- alpha.  At t = 0
  *                     (or for a fresh state) call ESIM_INIT first.
@@ -278,7 +289,8 @@ int esim_events(esim_plan plan, int32_t t, int32_t mode, const int64_t* worklist
  *                     regress the flagged pixels, each regression writing its
  *                     model straight into the state.  With an explicit
  *                     esim_threshold the models pass through the plan's
- *                     buffers (one more launch), so that bxy is written too.
+ *                     buffers (one more launch, so that bxy is written too)
+ *                     and a last launch sums rmom over the new planes.
  *   ESIM_EXHAUSTIVE:  regress every pixel, then eq. (1) on alpha (as
  *                     esim_events).
  *   ESIM_RAW:         eq. (1) on y_t.

@@ -49,7 +49,7 @@ class esim_params(ctypes.Structure):
 class esim_state(ctypes.Structure):
     _fields_ = [("alpha", ctypes.c_void_p), ("beta", ctypes.c_void_p),
                 ("xref", ctypes.c_void_p), ("tref", ctypes.c_void_p), ("last", ctypes.c_void_p),
-                ("bxy", ctypes.c_void_p)]
+                ("bxy", ctypes.c_void_p), ("rmom", ctypes.c_void_p)]
 
 
 class esim_events_buf(ctypes.Structure):
@@ -156,10 +156,11 @@ class State:
         self.tref = torch.zeros(HW, dtype=torch.int32, device=device)
         self.last = torch.zeros(HW, dtype=torch.float32, device=device)
         self.bxy = torch.zeros((2, HW), dtype=torch.float32, device=device)
+        self.rmom = torch.zeros((2, HW), dtype=torch.float32, device=device)
 
     def struct(self) -> esim_state:
         return esim_state(_ptr(self.alpha), _ptr(self.beta), _ptr(self.xref), _ptr(self.tref),
-                          _ptr(self.last), _ptr(self.bxy))
+                          _ptr(self.last), _ptr(self.bxy), _ptr(self.rmom))
 
 
 class Plan:

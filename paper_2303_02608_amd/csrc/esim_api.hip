@@ -102,19 +102,25 @@ bool full_state(esim_plan pl) {
     if (!c.st_beta || !c.st_xref || !c.st_alpha || !c.st_tref) return false;
   if (pl->thr != ESIM_THRESHOLD_CLOSED)
     for (const auto& c : pl->host)
-      if (!c.st_bxy) return false;
+      if (!c.st_bxy || !c.st_rmom) return false;
   return true;
 }
 
-// The explicit thresholds address every frame of a clip through one buffer
-// resource (32-bit offsets).
+// The explicit thresholds read the whole stored plane and its window sums.
 int explicit_ok(esim_plan pl) {
   if (pl->thr == ESIM_THRESHOLD_CLOSED) return ok();
   for (const auto& c : pl->host)
-    if (!c.st_bxy) return fail(ESIM_E_INVAL, "explicit thresholds need the state's bxy");
-  if (pl->max_feat_bytes >= (1ull << 32))
-    return fail(ESIM_E_UNSUPPORTED, "explicit thresholds need feature arrays below 4 GiB");
+    if (!c.st_bxy || !c.st_rmom) return fail(ESIM_E_INVAL, "explicit thresholds need the state's bxy and rmom");
   return ok();
+}
+
+// After models were stored at frame t (work-list items, or every pixel when
+// worklist is null): their window sums, for plans with an explicit threshold.
+int store_moments(esim_plan pl, int32_t t, const int64_t* worklist, const int32_t* count, hipStream_t s) {
+  if (pl->thr == ESIM_THRESHOLD_CLOSED) return ok();
+  return hip_check(esim::launch_moments(pl->dev, pl->nclips, pl->nblk, t, pl->F, pl->f16, worklist, count,
+                                        pl->wl_capacity, s),
+                   "window sums of the stored planes");
 }
 
 // Threshold at t into the plan's workspace, then the compaction (work list,
@@ -127,7 +133,7 @@ int threshold_compact(esim_plan pl, int32_t t, float* dl, int64_t* worklist, int
                      "threshold");
   int rc = explicit_ok(pl);
   if (rc != ESIM_OK) return rc;
-  rc = hip_check(esim::launch_explicit_flag(pl->dev, pl->nclips, pl->nblk, t, pl->F, pl->f16, dl, pl->ws,
+  rc = hip_check(esim::launch_explicit_flag(pl->dev, pl->nclips, pl->nblk, t, pl->F, pl->f16, pl->thr, dl, pl->ws,
                                             ev ? ev->count : nullptr, s),
                  "threshold(explicit)");
   if (rc != ESIM_OK) return rc;
@@ -231,6 +237,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
         cd.st_tref = states[c].tref;
         cd.st_last = states[c].last;
         cd.st_bxy = states[c].bxy;
+        cd.st_rmom = states[c].rmom;
       }
       cd.thr = p.threshold;
       cd.W = k.W;
@@ -458,7 +465,14 @@ int esim_events(esim_plan pl, int32_t t, int32_t mode, const int64_t* worklist, 
       if (!c.st_alpha) return fail(ESIM_E_INVAL, "state alpha is null");
     if (mode == ESIM_INIT) {
       if (alpha && n_out < pl->npix) return fail(ESIM_E_INVAL, "n_out < plan pixels");
-      return hip_check(esim::launch_init(pl->dev, pl->nclips, pl->nblk, t, alpha, beta, n_out, s), "init");
+      const bool model = alpha && beta && pl->thr != ESIM_THRESHOLD_CLOSED;
+      if (model) {
+        int rc = explicit_ok(pl);
+        if (rc != ESIM_OK) return rc;
+      }
+      int rc = hip_check(esim::launch_init(pl->dev, pl->nclips, pl->nblk, t, alpha, beta, n_out, s), "init");
+      if (rc != ESIM_OK || !model) return rc;
+      return store_moments(pl, t, nullptr, nullptr, s);
     }
     if (!ev || !ev->x || !ev->y || !ev->t || !ev->p || !ev->count || ev->capacity < 0)
       return fail(ESIM_E_INVAL, "events buffer incomplete");
@@ -469,9 +483,13 @@ int esim_events(esim_plan pl, int32_t t, int32_t mode, const int64_t* worklist, 
       if (n_out < 1) return fail(ESIM_E_INVAL, "n_out < 1");
       for (const auto& c : pl->host)
         if (!c.st_beta || !c.st_xref || !c.st_tref) return fail(ESIM_E_INVAL, "state incomplete");
-      return hip_check(esim::launch_list_events(pl->dev, pl->nclips, t, worklist, count, pl->wl_capacity,
-                                                dl, alpha, beta, n_out, pl->ws, ed, s),
-                       "events(thresholded)");
+      int rc = explicit_ok(pl);
+      if (rc != ESIM_OK) return rc;
+      rc = hip_check(esim::launch_list_events(pl->dev, pl->nclips, t, worklist, count, pl->wl_capacity, dl,
+                                              alpha, beta, n_out, pl->ws, ed, s),
+                     "events(thresholded)");
+      if (rc != ESIM_OK) return rc;
+      return store_moments(pl, t, worklist, count, s);
     }
     if (mode == ESIM_EXHAUSTIVE || mode == ESIM_RAW) {
       if (!multi_state_ok(pl)) return fail(ESIM_E_INVAL, "multi_crossing needs the state's last");
@@ -508,9 +526,11 @@ int esim_step(esim_plan pl, int32_t t, int32_t mode, float* dl, esim_events_buf*
       int rc = launch_plan_regress(pl, t, nullptr, nullptr, pl->npix, pl->step_alpha, pl->step_beta, nullptr,
                                    nullptr, false, s);
       if (rc != ESIM_OK) return rc;
-      return hip_check(esim::launch_init(pl->dev, pl->nclips, pl->nblk, t, pl->step_alpha, pl->step_beta,
-                                         pl->npix, s),
-                       "step(init)");
+      rc = hip_check(esim::launch_init(pl->dev, pl->nclips, pl->nblk, t, pl->step_alpha, pl->step_beta,
+                                       pl->npix, s),
+                     "step(init)");
+      if (rc != ESIM_OK) return rc;
+      return store_moments(pl, t, nullptr, nullptr, s);
     }
     if (!ev || !ev->x || !ev->y || !ev->t || !ev->p || !ev->count || ev->capacity < 0)
       return fail(ESIM_E_INVAL, "events buffer incomplete");
@@ -524,10 +544,12 @@ int esim_step(esim_plan pl, int32_t t, int32_t mode, float* dl, esim_events_buf*
       rc = launch_plan_regress(pl, t, pl->step_wl, pl->step_count, pl->wl_capacity, pl->step_alpha,
                                pl->step_beta, nullptr, nullptr, false, s);
       if (rc != ESIM_OK) return rc;
-      return hip_check(esim::launch_list_state(pl->dev, pl->nclips, t, pl->step_wl, pl->step_count,
-                                               pl->wl_capacity, pl->step_alpha, pl->step_beta,
-                                               pl->wl_capacity, s),
-                       "step(state)");
+      rc = hip_check(esim::launch_list_state(pl->dev, pl->nclips, t, pl->step_wl, pl->step_count,
+                                             pl->wl_capacity, pl->step_alpha, pl->step_beta, pl->wl_capacity,
+                                             s),
+                     "step(state)");
+      if (rc != ESIM_OK) return rc;
+      return store_moments(pl, t, pl->step_wl, pl->step_count, s);
     }
     if ((mode == ESIM_EXHAUSTIVE || mode == ESIM_RAW) && !multi_state_ok(pl))
       return fail(ESIM_E_INVAL, "multi_crossing needs the state's last");

@@ -1,24 +1,29 @@
-// Explicit Delta R threshold (Sec. 2.2: eq. (7) and the R of eq. (4) summed
-// over a window, instead of the closed form of Prop. 1).
+// Explicit Delta R thresholds (Sec. 2.2: eq. (7) and the R of eq. (4) as window
+// sums, instead of the closed form of Prop. 1).
 //
-//   explicit_flag_kernel  one lane per pixel of a 256-pixel block (the block
-//                         layout of the closed-form flag kernel, so the same
-//                         scatter compacts it).  With the stored plane
-//                         (alpha, beta over D: bxy and beta) and, in
-//                         bandwidth-scaled regressors v, theta_j = beta_j h b_j:
-//                           pass 1, the last-event window (frame t_ref, centre
-//                           x^c = the features at t_ref):
-//                             r_i    = y_i - alpha - theta^T v_i
-//                             rhat_i = r_i + beta^T (x_hat^c - x^c)
-//                           (last-window reading: R, R_hat and the mean of
-//                           rhat all come from this pass);
-//                           pass 2 (new-window reading), frame t's window with
-//                           weights and v about x_hat^c:
-//                             rhat_i = y_i - alpha - theta^T v_i
+// In bandwidth-scaled regressors v (theta_j = beta_j h b_j) the stored plane
+// predicts alpha + theta^T v, and over a window of frame tt about the centre
+// (p, tt) a sample's residual is r_i = y_i - alpha - theta^T v_i.
+//
+//   moments_*_kernel      when a model is stored (frame t, uniform over the
+//                         launch): W, sum w r, sum w r^2 over the plane's own
+//                         window -> rmom = (R, m1 = sum w r / W).  Dense: one
+//                         lane per pixel (a wave reads 64 neighbouring
+//                         windows); work lists (scattered pixels): 16 lanes
+//                         per item, one window column each, summed with DPP.
+//   explicit_flag_kernel  per pixel at frame t, with d = beta^T (x_hat^c - x^c)
+//                         over the F buffer channels:
+//                           last-event window: the samples stay those of t_ref
+//                           and every translated residual is r_i + d, so
+//                           R_hat = R + 2 d m1 + d^2 and the mean is m1 + d;
+//                           frame t's window: W, sum w r_hat, sum w r_hat^2
+//                           summed over the window of frame t about x_hat^c;
 //                         Delta R = |R_hat - R|; flag when Delta R >= C^2;
-//                         dl = s sqrt(Delta R), s the sign of the weighted
-//                         mean of rhat (-1 when 0).  Sums in FP64, weights in
-//                         FP32 from the regression's window loop.
+//                         dl = s sqrt(Delta R), s the sign of the mean (-1 when
+//                         0).  Fills the ballots and block counts of the
+//                         closed-form flag kernel (same block layout), so the
+//                         same scatter compacts it.
+// Sums in FP64; weights in FP32 from the regression's window loop.
 #include <cmath>
 #include <cstdint>
 
@@ -29,7 +34,107 @@
 namespace esim {
 namespace {
 
+// The stored plane of pixel p in scaled regressors.
+template <int F>
+struct Plane {
+  double alpha, thx, thy, th[F];
+};
+
+template <int F>
+__device__ __forceinline__ void load_plane(const ClipDev& C, int64_t p, Plane<F>& P) {
+  P.alpha = C.st_alpha[p];
+  P.thx = static_cast<double>(C.st_bxy[p]) / C.sf[0];
+  P.thy = static_cast<double>(C.st_bxy[C.HW + p]) / C.sf[1];
+#pragma unroll
+  for (int f = 0; f < F; ++f) P.th[f] = static_cast<double>(C.st_beta[f * C.HW + p]) / C.sf[2 + f];
+}
+
+// W, sum w r, sum w r^2 of the plane over the window of frame tt about the
+// centre (pix, tt) (weights and v about that centre's feature vector); with
+// L > 1 lane j of the item's L-lane group takes the columns j, j + L, ...
+// and the sums are of those columns.
+template <int F, bool F16, int L = 1>
+__device__ __forceinline__ void window_sums(const ClipDev& C, int64_t pix, int tt, bool active,
+                                            const Plane<F>& P, double& sw, double& s1, double& s2,
+                                            int j = 0) {
+  ItemGeom<F, F16, double> g;
+  make_geom(g, C, pix, tt, max(0, tt - C.tr), min(C.T, tt + C.tr + 1), active);
+  double base = P.alpha;                  // alpha + th_x v_x of the column pass
+  sw = s1 = s2 = 0.0;
+  window_loop<F, L>(
+      g, j, [&](double vx) { base = fma(P.thx, vx, P.alpha); },
+      [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+        double pr = fma(P.thy, vy, base);
+#pragma unroll
+        for (int f = 0; f < F; ++f) pr = fma(P.th[f], v[f], pr);
+        const double r = yd - pr;
+        const double wr = w * r;
+        sw += w;
+        s1 += wr;
+        s2 = fma(wr, r, s2);
+      },
+      [&](double) {});
+}
+
+template <int F, bool F16, int L>
+__device__ __forceinline__ void store_moments(const ClipDev& C, int64_t p, int t, bool active, int j) {
+  Plane<F> P;
+  load_plane<F>(C, p, P);
+  double sw, s1, s2;
+  window_sums<F, F16, L>(C, p, t, active, P, sw, s1, s2, j);
+  sw = group_sum<L>(sw);
+  s1 = group_sum<L>(s1);
+  s2 = group_sum<L>(s2);
+  if (active && j == 0) {
+    C.st_rmom[p] = static_cast<float>(s2 / sw);
+    C.st_rmom[C.HW + p] = static_cast<float>(s1 / sw);
+  }
+}
+
+constexpr int kListLanes = 16;                   // lanes per work-list item
+constexpr int kItemsPerBlock = kBlock / kListLanes;
+
+// Dense: every pixel of the plan, in the flag kernel's block layout.
 template <int F, bool F16>
+__global__ void __launch_bounds__(kBlock)
+moments_dense_kernel(const ClipDev* __restrict__ clips, int nclips, int t) {
+  const int64_t b = blockIdx.x;
+  const ClipDev& C = clips[block_clip(clips, nclips, b)];
+  const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
+  if (t < 0 || t >= C.T) return;                 // uniform in the block
+  const bool active = p < C.HW;
+  store_moments<F, F16, 1>(C, active ? p : 0, t, active, 0);
+}
+
+// Work list: kListLanes lanes per item, grid-stride over the items.
+template <int F, bool F16>
+__global__ void __launch_bounds__(kBlock)
+moments_list_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const int64_t* __restrict__ worklist,
+                    const int32_t* __restrict__ count, int64_t max_items) {
+  const int64_t n = max(static_cast<int64_t>(0), min(static_cast<int64_t>(count[0]), max_items));
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * kItemsPerBlock;
+  const int j = threadIdx.x % kListLanes;
+  for (int64_t i0 = static_cast<int64_t>(blockIdx.x) * kItemsPerBlock; i0 < n; i0 += stride) {
+    const int64_t i = i0 + threadIdx.x / kListLanes;
+    const int64_t it = i < n ? worklist[i] : -1;
+    const int cl = it < 0 ? -1 : item_clip(it);
+    bool pending = it >= 0 && cl < nclips;
+    // one pass per clip present in the wave (almost always one), so that the
+    // clip descriptor is wave-uniform
+    while (__ballot(pending)) {
+      const int src = __ffsll(static_cast<unsigned long long>(__ballot(pending))) - 1;
+      const int cw = __builtin_amdgcn_readfirstlane(__shfl(cl, src));
+      const ClipDev& C = clips[cw];
+      const bool mine = pending && cl == cw;
+      const int64_t p = mine ? item_pixel(it) : 0;
+      const bool active = mine && p < C.HW && t < C.T;
+      store_moments<F, F16, kListLanes>(C, active ? p : 0, t < C.T ? t : 0, active, j);
+      pending = pending && !mine;
+    }
+  }
+}
+
+template <int F, bool F16, bool NEW>
 __global__ void __launch_bounds__(kBlock)
 explicit_flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, float* __restrict__ dl,
                      Workspace ws, const int64_t* __restrict__ ev_count) {
@@ -43,68 +148,28 @@ explicit_flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, float
   bool flag = false, pos = false;
   if (frame_ok) {
     const int64_t pc = in ? p : 0;              // idle lanes read pixel 0 with weight 0
-    const int tref = min(max(C.st_tref[pc], 0), C.T - 1);
-    // the plane in scaled regressors: pred = alpha + sum_j th_j v_j
-    const double alpha = C.st_alpha[pc];
-    const double thx = static_cast<double>(C.st_bxy[pc]) / C.sf[0];
-    const double thy = static_cast<double>(C.st_bxy[C.HW + pc]) / C.sf[1];
-    double th[F];
-    double shift = 0.0;                         // beta^T (x_hat^c - x^c)
-#pragma unroll
-    for (int f = 0; f < F; ++f) {
-      const double bf = C.st_beta[f * C.HW + pc];
-      th[f] = bf / C.sf[2 + f];
-      shift = fma(bf, static_cast<double>(feat_value(C, t, f, pc)) - C.st_xref[f * C.HW + pc], shift);
-    }
-    const bool new_window = C.thr == ESIM_THRESHOLD_NEW_WINDOW;
-    double sw = 0.0, sr2 = 0.0, sh = 0.0, sh2 = 0.0;
-    double base = alpha;                        // alpha + th_x v_x of the column pass
-    {
-      ItemGeom<F, F16, double> g;
-      make_geom(g, C, pc, tref, 0, C.T, in);
-      window_loop<F, 1>(
-          g, 0, [&](double vx) { base = fma(thx, vx, alpha); },
-          [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-            double pr = fma(thy, vy, base);
-#pragma unroll
-            for (int f = 0; f < F; ++f) pr = fma(th[f], v[f], pr);
-            const double r = yd - pr;
-            const double rh = r + shift;
-            const double wr = w * r, wh = w * rh;
-            sw += w;
-            sr2 = fma(wr, r, sr2);
-            sh += wh;
-            sh2 = fma(wh, rh, sh2);
-          },
-          [&](double) {});
-    }
-    const double R = sr2 / sw;
-    double Rh = sh2 / sw, mean = sh / sw;
-    if (new_window) {
-      ItemGeom<F, F16, double> g;
-      make_geom(g, C, pc, t, 0, C.T, in);
-      double sw2 = 0.0, s1 = 0.0, s2 = 0.0;
-      window_loop<F, 1>(
-          g, 0, [&](double vx) { base = fma(thx, vx, alpha); },
-          [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-            double pr = fma(thy, vy, base);
-#pragma unroll
-            for (int f = 0; f < F; ++f) pr = fma(th[f], v[f], pr);
-            const double rh = yd - pr;
-            const double wh = w * rh;
-            sw2 += w;
-            s1 += wh;
-            s2 = fma(wh, rh, s2);
-          },
-          [&](double) {});
-      Rh = s2 / sw2;
-      mean = s1 / sw2;
+    double d = 0.0;                             // beta^T (x_hat^c - x^c)
+    for (int f = 0; f < F; ++f)
+      d = fma(static_cast<double>(C.st_beta[f * C.HW + pc]),
+              static_cast<double>(feat_value(C, t, f, pc)) - C.st_xref[f * C.HW + pc], d);
+    const double R = C.st_rmom[pc], m1 = C.st_rmom[C.HW + pc];
+    double dR, mean;
+    if constexpr (NEW) {
+      Plane<F> P;
+      load_plane<F>(C, pc, P);
+      double sw, s1, s2;
+      window_sums<F, F16, 1>(C, pc, t, in, P, sw, s1, s2);
+      dR = s2 / sw - R;
+      mean = s1 / sw;
+    } else {
+      dR = d * (2.0 * m1 + d);
+      mean = m1 + d;
     }
     if (in) {
-      const double d = fabs(Rh - R);
-      flag = d >= C.C * C.C;
+      const double a = fabs(dR);
+      flag = a >= C.C * C.C;
       pos = mean > 0.0;
-      if (dl) dl[C.pix_off + p] = static_cast<float>(pos ? sqrt(d) : -sqrt(d));
+      if (dl) dl[C.pix_off + p] = static_cast<float>(pos ? sqrt(a) : -sqrt(a));
     }
   } else if (p < C.HW && dl) {
     dl[C.pix_off + p] = __builtin_nanf("");
@@ -127,26 +192,38 @@ explicit_flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, float
 }
 
 using ExplicitFn = void (*)(const ClipDev*, int, int, float*, Workspace, const int64_t*);
+using MomentsDenseFn = void (*)(const ClipDev*, int, int);
+using MomentsListFn = void (*)(const ClipDev*, int, int, const int64_t*, const int32_t*, int64_t);
 
 template <int F>
-constexpr ExplicitFn pick(bool f16) {
-  return f16 ? explicit_flag_kernel<F, true> : explicit_flag_kernel<F, false>;
-}
+struct Pick {
+  static ExplicitFn flag(bool f16, bool nw) {
+    return f16 ? (nw ? explicit_flag_kernel<F, true, true> : explicit_flag_kernel<F, true, false>)
+               : (nw ? explicit_flag_kernel<F, false, true> : explicit_flag_kernel<F, false, false>);
+  }
+  static MomentsDenseFn dense(bool f16) {
+    return f16 ? moments_dense_kernel<F, true> : moments_dense_kernel<F, false>;
+  }
+  static MomentsListFn list(bool f16) {
+    return f16 ? moments_list_kernel<F, true> : moments_list_kernel<F, false>;
+  }
+};
 
-ExplicitFn explicit_kernel(int F, bool f16) {
+template <template <int> class P, class Fn>
+auto by_f(int F, Fn&& fn) -> decltype(fn(P<1>{})) {
   switch (F) {
-    case 1: return pick<1>(f16);
-    case 2: return pick<2>(f16);
-    case 3: return pick<3>(f16);
-    case 4: return pick<4>(f16);
-    case 5: return pick<5>(f16);
-    case 6: return pick<6>(f16);
-    case 7: return pick<7>(f16);
-    case 8: return pick<8>(f16);
-    case 9: return pick<9>(f16);
-    case 10: return pick<10>(f16);
-    case 11: return pick<11>(f16);
-    case 12: return pick<12>(f16);
+    case 1: return fn(P<1>{});
+    case 2: return fn(P<2>{});
+    case 3: return fn(P<3>{});
+    case 4: return fn(P<4>{});
+    case 5: return fn(P<5>{});
+    case 6: return fn(P<6>{});
+    case 7: return fn(P<7>{});
+    case 8: return fn(P<8>{});
+    case 9: return fn(P<9>{});
+    case 10: return fn(P<10>{});
+    case 11: return fn(P<11>{});
+    case 12: return fn(P<12>{});
     default: return nullptr;
   }
 }
@@ -154,11 +231,32 @@ ExplicitFn explicit_kernel(int F, bool f16) {
 }  // namespace
 
 hipError_t launch_explicit_flag(const ClipDev* clips, int nclips, int64_t nblk, int t, int F, bool f16,
-                                float* dl, const Workspace& ws, const int64_t* ev_count, hipStream_t s) {
-  const ExplicitFn k = explicit_kernel(F, f16);
+                                int thr, float* dl, const Workspace& ws, const int64_t* ev_count,
+                                hipStream_t s) {
+  const bool nw = thr == ESIM_THRESHOLD_NEW_WINDOW;
+  const ExplicitFn k = by_f<Pick>(F, [&](auto p) { return decltype(p)::flag(f16, nw); });
   if (!k) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips, t, dl, ws,
                      ev_count);
+  return hipGetLastError();
+}
+
+hipError_t launch_moments(const ClipDev* clips, int nclips, int64_t nblk, int t, int F, bool f16,
+                          const int64_t* worklist, const int32_t* count, int64_t max_items,
+                          hipStream_t s) {
+  if (!worklist) {
+    const MomentsDenseFn k = by_f<Pick>(F, [&](auto p) { return decltype(p)::dense(f16); });
+    if (!k) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips, t);
+    return hipGetLastError();
+  }
+  const MomentsListFn k = by_f<Pick>(F, [&](auto p) { return decltype(p)::list(f16); });
+  if (!k) return hipErrorInvalidValue;
+  int64_t blocks = (max_items + kItemsPerBlock - 1) / kItemsPerBlock;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(k, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, clips, nclips, t, worklist,
+                     count, max_items);
   return hipGetLastError();
 }
 

@@ -36,6 +36,7 @@ struct ClipDev {
   double sf[ESIM_MAX_D];   // 1 / (h b_j)
   double gbk[ESIM_MAX_D];  // 1 / (h^2 b_j^3)
   float* st_bxy;           // [2][HW] coordinate components of beta (nullable)
+  float* st_rmom;          // [2][HW] R and mean residual of the stored plane (nullable)
   int32_t thr;             // esim_threshold
 };
 
@@ -205,6 +206,13 @@ hipError_t launch_nn(const NnArgs& a, hipStream_t s);
 // dl and the flag/polarity ballots and block counts of the compaction
 // workspace, like the closed-form flag kernel.
 hipError_t launch_explicit_flag(const ClipDev* clips, int nclips, int64_t nblk, int t, int F, bool f16,
-                                float* dl, const Workspace& ws, const int64_t* ev_count, hipStream_t s);
+                                int thr, float* dl, const Workspace& ws, const int64_t* ev_count,
+                                hipStream_t s);
+// Window sums (R, mean residual) of the stored planes of the pixels updated at
+// frame t: the work-list items (worklist non-null, *count of them, at most
+// max_items) or every pixel of the plan (dense, nblk kBlock-pixel blocks).
+hipError_t launch_moments(const ClipDev* clips, int nclips, int64_t nblk, int t, int F, bool f16,
+                          const int64_t* worklist, const int32_t* count, int64_t max_items,
+                          hipStream_t s);
 
 }  // namespace esim

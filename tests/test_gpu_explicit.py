@@ -121,6 +121,7 @@ def test_explicit_step_equals_separate_calls_and_graph(small_clip, form):
         assert np.array_equal(ea[k], eb[k]), k
     for k in ("alpha", "beta", "xref", "tref", "bxy"):
         assert torch.equal(getattr(a.state, k), getattr(b.state, k)), k
+    assert torch.equal(a.state.rmom, b.state.rmom)
     a.capture("thresholded")
     for _ in range(2):
         a.replay()
@@ -131,18 +132,51 @@ def test_explicit_step_equals_separate_calls_and_graph(small_clip, form):
         _ = (y * 2).sum().item()
 
 
-def test_explicit_needs_bxy(small_clip):
+@pytest.mark.parametrize("missing", ["bxy", "rmom"])
+def test_explicit_needs_the_whole_plane(small_clip, missing):
     E, feat, cfg = small_clip["E"], small_clip["feat"], small_clip["cfg"]
-    say("explicit threshold without bxy")
+    say(f"explicit threshold without {missing}")
     y, fd = to_dev(E, feat)
     T, F, H, W = feat.shape
     st = B.State(H, W, F, fd.device)
-    st.bxy = None
+    setattr(st, missing, None)
     plan = B.Plan([y], [fd], [_params(cfg, "new")], [st])
     dl = torch.empty(H * W, device=fd.device)
     wl = torch.empty(H * W, dtype=torch.int64, device=fd.device)
     cnt = torch.zeros(2, dtype=torch.int32, device=fd.device)
+    a = torch.empty(H * W, device=fd.device)
+    b = torch.empty((F + 2, H * W), device=fd.device)
     with pytest.raises(B.EsimError):
         B.threshold(plan, 1, dl, wl, cnt)
     with pytest.raises(B.EsimError):
         B.step(plan, 0, B.INIT)
+    with pytest.raises(B.EsimError):
+        B.events(plan, 0, B.INIT, None, alpha=a, beta=b, n_out=H * W)
+
+
+@pytest.mark.parametrize("form", ["last", "new"])
+def test_explicit_batch_equals_single_clips(form):
+    """A plan of clips of uneven size, length and radius: a work list (and the
+    window sums over it) then spans several clips; every clip's events equal
+    its own single-clip run, fused and unfused."""
+    from paper_2303_02608_amd.simulator import BatchSimulator
+    say(f"explicit {form}: batch of uneven clips")
+    shapes = [(40, 30, 9, 3, 1), (23, 57, 12, 4, 0), (64, 48, 6, 9, 1), (50, 50, 5, 2, 1)]
+    clips = []
+    for i, (W, H, T, r, tr) in enumerate(shapes):
+        spec = synth.ClipSpec(W=W, H=H, T=T, spp=2 + i, F=7, n_discs=2 + i, speed=(0.5, 2.0),
+                              seed=6000 + i)
+        d = synth.make_clip(spec)
+        y, fd = to_dev(d["E"].numpy(), d["feat"].numpy())
+        clips.append((y, fd, B.Params(r=r, tr=tr, C=0.2, threshold=FORMS[form][0])))
+    bs = BatchSimulator([c[0] for c in clips], [c[1] for c in clips], [c[2] for c in clips])
+    got = bs.run()
+    sep = bs.run(fused=False)
+    assert got["count"] > 0
+    for k in ("x", "y", "t", "p", "clip"):
+        assert np.array_equal(got[k], sep[k]), k
+    for c, (y, fd, p) in enumerate(clips):
+        m = got["clip"] == c
+        single = Simulator(y, fd, p).run("thresholded")
+        for k in ("x", "y", "t", "p"):
+            assert np.array_equal(got[k][m], single[k]), (c, k)
