@@ -57,6 +57,32 @@ def test_dvs_events_on_sampled_pixels(dvs, mode):
     assert orc["count"] > 0
 
 
+@pytest.mark.parametrize("form", ["last", "new"])
+def test_dvs_explicit_thresholds_on_sampled_pixels(dvs, form):
+    """The explicit Delta R thresholds on the whole DVS clip (the launch
+    configuration of the threshold-forms workload) against the oracle's
+    explicit runs on sampled pixels; band as in the small-workload test."""
+    cfg = dvs["cfg"]
+    thr, omode = ((B.THRESHOLD_LAST_WINDOW, oracle.EXPLICIT_LAST) if form == "last"
+                  else (B.THRESHOLD_NEW_WINDOW, oracle.EXPLICIT_NEW))
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"], threshold=thr)
+    sim = Simulator(dvs["y"], dvs["feat"], p)
+    sched = autotune.tune(sim.plan)
+    say(f"DVS explicit threshold {form}, schedule {sched}")
+    gpu = sim.run("thresholded")
+    T, F, H, W = dvs["fn"].shape
+    rng = np.random.default_rng(13)
+    fired = np.unique(gpu["y"].astype(np.int64) * W + gpu["x"])
+    pix = np.unique(np.concatenate([rng.choice(H * W, 48, replace=False),
+                                    rng.choice(fired, min(48, fired.size), replace=False)]))
+    orc = oracle.run(_oracle_clip(dvs), oracle.Params(p.r, p.tr, p.C), omode, pixels=pix, want_dl=True)
+    n, exc, fails = compare_events(gpu, orc, W, p.C, 1e-3, pixels=pix)
+    say(f"DVS explicit {form}: {n} sampled pixels, {orc['count']} oracle events, excused {exc}")
+    assert not fails, fails[:5]
+    assert exc <= 2
+    assert orc["count"] > 0
+
+
 def test_dvs_sampled_regressions(dvs):
     cfg = dvs["cfg"]
     p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"])
