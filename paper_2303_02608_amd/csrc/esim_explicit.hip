@@ -8,16 +8,18 @@
 //   moments_*_kernel      when a model is stored (frame t, uniform over the
 //                         launch): W, sum w r, sum w r^2 over the plane's own
 //                         window -> rmom = (R, m1 = sum w r / W).  Dense: one
-//                         lane per pixel (a wave reads 64 neighbouring
-//                         windows); work lists (scattered pixels): 16 lanes
-//                         per item, one window column each, summed with DPP.
+//                         lane per pixel, row-major window walk (a wave reads
+//                         64 neighbouring pixels of a row); work lists
+//                         (scattered pixels): 16 lanes per item, one window
+//                         column each, summed with DPP.
 //   explicit_flag_kernel  per pixel at frame t, with d = beta^T (x_hat^c - x^c)
 //                         over the F buffer channels:
 //                           last-event window: the samples stay those of t_ref
 //                           and every translated residual is r_i + d, so
 //                           R_hat = R + 2 d m1 + d^2 and the mean is m1 + d;
 //                           frame t's window: W, sum w r_hat, sum w r_hat^2
-//                           summed over the window of frame t about x_hat^c;
+//                           summed over the window of frame t about x_hat^c
+//                           (row-major walk);
 //                         Delta R = |R_hat - R|; flag when Delta R >= C^2;
 //                         dl = s sqrt(Delta R), s the sign of the mean (-1 when
 //                         0).  Fills the ballots and block counts of the
@@ -76,6 +78,72 @@ __device__ __forceinline__ void window_sums(const ClipDev& C, int64_t pix, int t
       [&](double) {});
 }
 
+// The same sums with one lane per pixel, walking the window row by row
+// (columns innermost): the 64 lanes of a wave read 64 neighbouring pixels of
+// one row, and the 2r + 1 shifted reads of that row hit the same cache lines,
+// where a column-major walk would fetch every row once per column pass.
+// Samples outside the image read the centre with weight 0.
+template <int F, bool F16>
+__device__ __forceinline__ void window_sums_rows(const ClipDev& C, int64_t pix, int tt, bool active,
+                                                 const Plane<F>& P, double& sw, double& s1, double& s2) {
+  constexpr uint32_t ES = F16 ? 2u : 4u;
+  constexpr double K = kHalfLog2e;
+  const int W = C.W, H = C.H, r = C.r;
+  const uint32_t HW = static_cast<uint32_t>(C.HW);
+  const int f0 = max(0, tt - C.tr), f1 = min(C.T, tt + C.tr + 1);
+  const __amdgpu_buffer_rsrc_t ry =
+      make_rsrc(C.y + static_cast<uint64_t>(f0) * HW, static_cast<uint64_t>(f1 - f0) * HW * 4u);
+  const __amdgpu_buffer_rsrc_t rf =
+      make_rsrc(static_cast<const char*>(C.feat) + static_cast<uint64_t>(f0) * F * HW * ES,
+                static_cast<uint64_t>(f1 - f0) * F * HW * ES);
+  const int py = static_cast<int>(pix / W), px = static_cast<int>(pix - static_cast<int64_t>(py) * W);
+  const uint32_t fc = static_cast<uint32_t>(tt - f0);
+  double sf[F], xcs[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) {
+    sf[f] = C.sf[2 + f];
+    xcs[f] = static_cast<double>(ld_feat<F16>(rf, (fc * F * HW + static_cast<uint32_t>(pix)) * ES,
+                                              f * HW * ES)) * sf[f];
+  }
+  const double vxs = C.sf[0] / r, vys = C.sf[1] / r;
+  sw = s1 = s2 = 0.0;
+  for (int fr = 0; fr < f1 - f0; ++fr) {
+    for (int dy = -r; dy <= r; ++dy) {
+      const int row = py + dy;
+      const bool row_ok = active && row >= 0 && row < H;
+      const double vy = dy * vys;
+      const double ky = K * vy * vy;
+      const double by = fma(P.thy, vy, P.alpha);
+#pragma unroll 3
+      for (int dx = -r; dx <= r; ++dx) {
+        const int col = px + dx;
+        const bool ok = row_ok && col >= 0 && col < W;
+        // frame (relative to f0) and pixel of the sample, or the centre
+        const uint32_t fs = ok ? static_cast<uint32_t>(fr) : fc;
+        const uint32_t ps = ok ? static_cast<uint32_t>(row * W + col) : static_cast<uint32_t>(pix);
+        const uint32_t fe = fs * F * HW + ps;
+        const float yv = ld_f32(ry, (fs * HW + ps) * 4u, 0);
+        double q = 0.0, pr = fma(P.thx, dx * vxs, by);
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          const double v = fma(static_cast<double>(ld_feat<F16>(rf, fe * ES, f * HW * ES)), sf[f], -xcs[f]);
+          q = fma(v, v, q);
+          pr = fma(P.th[f], v, pr);
+        }
+        const double vx = dx * vxs;
+        const float ew = __builtin_amdgcn_exp2f(static_cast<float>(fma(q, K, fma(K * vx, vx, ky))));
+        const double w = ok ? static_cast<double>(ew) : 0.0;
+        const double res = static_cast<double>(yv) - pr;
+        const double wr = w * res;
+        sw += w;
+        s1 += wr;
+        s2 = fma(wr, res, s2);
+      }
+    }
+  }
+}
+
+// Work-list form: L lanes per item over the regression's column-major loop.
 template <int F, bool F16, int L>
 __device__ __forceinline__ void store_moments(const ClipDev& C, int64_t p, int t, bool active, int j) {
   Plane<F> P;
@@ -103,7 +171,15 @@ moments_dense_kernel(const ClipDev* __restrict__ clips, int nclips, int t) {
   const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
   if (t < 0 || t >= C.T) return;                 // uniform in the block
   const bool active = p < C.HW;
-  store_moments<F, F16, 1>(C, active ? p : 0, t, active, 0);
+  const int64_t pc = active ? p : 0;
+  Plane<F> P;
+  load_plane<F>(C, pc, P);
+  double sw, s1, s2;
+  window_sums_rows<F, F16>(C, pc, t, active, P, sw, s1, s2);
+  if (active) {
+    C.st_rmom[p] = static_cast<float>(s2 / sw);
+    C.st_rmom[C.HW + p] = static_cast<float>(s1 / sw);
+  }
 }
 
 // Work list: kListLanes lanes per item, grid-stride over the items.
@@ -158,7 +234,7 @@ explicit_flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, float
       Plane<F> P;
       load_plane<F>(C, pc, P);
       double sw, s1, s2;
-      window_sums<F, F16, 1>(C, pc, t, in, P, sw, s1, s2);
+      window_sums_rows<F, F16>(C, pc, t, in, P, sw, s1, s2);
       dR = s2 / sw - R;
       mean = s1 / sw;
     } else {
