@@ -180,3 +180,44 @@ def test_explicit_batch_equals_single_clips(form):
         single = Simulator(y, fd, p).run("thresholded")
         for k in ("x", "y", "t", "p"):
             assert np.array_equal(got[k][m], single[k]), (c, k)
+
+
+@pytest.mark.parametrize("form", ["last", "new"])
+@pytest.mark.parametrize("F,feat_dtype,r,tr", [(1, "f32", 4, 1), (12, "f32", 3, 1), (7, "f16", 5, 1),
+                                              (10, "f16", 8, 2)])
+def test_explicit_feature_counts_and_f16(form, F, feat_dtype, r, tr):
+    """The explicit forms at the extreme feature counts and with FP16 feature
+    storage (the oracle decodes the same FP16 bits); r = 8 takes the work-list
+    window sums over two column passes of the 16 lanes."""
+    W, H, T = 48, 40, 8
+    d = synth.random_features_clip(W, H, T, F, seed=70 + F, feat_dtype=feat_dtype)
+    E, feat = d["E"].numpy(), d["feat"].numpy()
+    p = B.Params(r=r, tr=tr, C=0.1, threshold=FORMS[form][0])
+    say(f"explicit {form} F={F} {feat_dtype} r={r} tr={tr}")
+    gpu, _ = run_gpu(E, feat, p, "thresholded", keep_dl=True)
+    orc = oracle.run(oracle_clip(E, feat), oracle.Params(p.r, p.tr, p.C, p.h, p.b, p.ridge),
+                     FORMS[form][1], want_dl=True)
+    n, excused, fails = compare_events(gpu, orc, W, p.C, BAND)
+    say(f"gpu {gpu['count']} oracle {orc['count']} excused {excused}")
+    assert gpu["count"] > 0
+    assert not fails and excused <= max(2, n // 1000), fails[:5]
+
+
+@pytest.mark.parametrize("form", ["last", "new"])
+def test_explicit_with_compensated_fp32_regression(small_clip, form):
+    """The explicit forms over the compensated-FP32 regression (models through
+    the plan's buffers at 16 and 4 lanes): the step equals the separate calls
+    bit for bit and the window sums are finite."""
+    E, feat, cfg = small_clip["E"], small_clip["feat"], small_clip["cfg"]
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"], precision=B.GRAM_F32C, threshold=FORMS[form][0])
+    say(f"explicit {form} with the compensated-FP32 regression")
+    y, fd = to_dev(E, feat)
+    a = Simulator(y, fd, p)
+    b = Simulator(y, fd, p)
+    ea = a.run("thresholded", fused=True)
+    eb = b.run("thresholded", fused=False)
+    assert ea["count"] == eb["count"] > 0
+    for k in ("x", "y", "t", "p"):
+        assert np.array_equal(ea[k], eb[k]), k
+    assert torch.equal(a.state.rmom, b.state.rmom)
+    assert torch.isfinite(a.state.rmom).all()
