@@ -70,6 +70,9 @@ def _L():
         _lib.orc_residual_hat.restype = dbl
         _lib.orc_explicit.argtypes = [vp, vp, i32, i32, i32, i32, i32, vp, vp]
         _lib.orc_explicit.restype = i32
+        _lib.orc_log_variance.argtypes = [vp, vp, i32, vp, i64, dbl]
+        _lib.orc_regress_bandwidth.argtypes = [vp, vp, vp, i32, vp, vp, i64, vp, vp, vp, vp, i32]
+        _lib.orc_regress_bandwidth.restype = i32
         _lib.orc_cond.argtypes = [vp, i32]
         _lib.orc_cond.restype = dbl
         _lib.orc_run.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp,
@@ -214,6 +217,39 @@ def explicit(clip: Clip, p: Params, new_window: bool, t_ref: int, t: int, px: in
                            px, py, theta.ctypes.data, out.ctypes.data)
     assert rc == 0, rc
     return dict(R=float(out[0]), R_hat=float(out[1]), mean=float(out[2]), change=float(out[3]))
+
+
+def log_variance(E: np.ndarray, var: np.ndarray, spp: int, eps: float = 1e-3) -> np.ndarray:
+    """Variance of y = log(E + eps) for the mean E of spp samples whose unbiased
+    sample variance is var (delta method): var / spp / (E + eps)^2."""
+    E = np.ascontiguousarray(E, dtype=np.float32)
+    var = np.ascontiguousarray(var, dtype=np.float32)
+    vy = np.empty(E.shape, np.float64)
+    _L().orc_log_variance(E.ctypes.data, var.ctypes.data, int(spp), vy.ctypes.data, E.size, eps)
+    return vy
+
+
+def regress_bandwidth(clip: Clip, p: Params, hs, vy: np.ndarray, items: np.ndarray,
+                      nthreads: int = 0):
+    """The bandwidth-optimised regression (Sec. 3, bandwidth optimisation; the
+    estimator is a reading): for each item (t*H*W + pixel) the candidate global
+    bandwidth h of eq. (5) with the smallest SURE_k = (alpha_k - y_c)^2 +
+    2 vy_c v_0 / W_k - vy_c, v = A^{-1} e_0.  Returns dict(theta [n][P], h [n],
+    alpha_k [n][K], sure [n][K], fails)."""
+    cp, b = _params(clip, p)
+    hs = np.ascontiguousarray(hs, dtype=np.float64)
+    vy = np.ascontiguousarray(vy, dtype=np.float64)
+    assert vy.shape == (clip.T, clip.H, clip.W)
+    items = np.ascontiguousarray(items, dtype=np.int64)
+    n, K = items.size, hs.size
+    theta = np.empty((n, clip.P))
+    h = np.empty(n)
+    ak = np.empty((n, K))
+    sk = np.empty((n, K))
+    fails = _L().orc_regress_bandwidth(ctypes.byref(clip._c), ctypes.byref(cp), hs.ctypes.data, K,
+                                       vy.ctypes.data, items.ctypes.data, n, theta.ctypes.data,
+                                       h.ctypes.data, ak.ctypes.data, sk.ctypes.data, nthreads)
+    return dict(theta=theta, h=h, alpha_k=ak, sure=sk, fails=fails)
 
 
 def cond(A: np.ndarray) -> float:

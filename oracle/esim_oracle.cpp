@@ -26,6 +26,14 @@
 //                          eqs. (4)-(5) by implicit differentiation).
 //   * orc_cond             2-norm condition number by cyclic Jacobi, for
 //                          reporting only.
+//   * orc_log_variance     variance of y = log(E_mean + eps) from the sample
+//                          variance of the radiance (delta method).
+//   * orc_regress_bandwidth the bandwidth-optimised variant of Sec. 3
+//                          (bandwidth optimisation): per regression, the
+//                          global bandwidth h of eq. (5) chosen from a
+//                          candidate set by the smallest estimated mean
+//                          squared error of alpha (Stein's unbiased risk
+//                          estimate with the MC variance of the centre).
 //
 // Readings of the paper taken here (where it is silent or loose):
 //   - Gaussian fall-off w(u) = exp(-u^2/2); the product over dimensions of
@@ -46,6 +54,14 @@
 //     frame, and the reference model is replaced by the new regression.
 //   - Exhaustive and raw baselines: L_ref starts at frame 0; an event fires
 //     when |L_t - L_ref| >= C, then L_ref <- L_t.
+//   - Bandwidth optimisation (the paper names the bias and the MC variance
+//     as the criterion but not the estimator): alpha_h = e_0^T A_h^{-1} g_h is
+//     linear in the observations, with d alpha_h / d y_c = (w_c / W_h) v_0,
+//     v = A_h^{-1} e_0 (w_c = 1, z_c = e_0 at the centre).  With sigma_c^2 the
+//     MC variance of y_c, SURE(h) = (alpha_h - y_c)^2 + 2 sigma_c^2 v_0 / W_h
+//     - sigma_c^2 estimates E[(alpha_h - f_c)^2] without bias (bias^2 plus
+//     variance); the candidate with the smallest SURE is taken (the first of
+//     equal ones).  Only h is optimised; b stays as given.
 //   - Explicit thresholds (an ablation of Prop. 1): Delta R = |R_hat - R| is
 //     evaluated from its definition instead of the closed form.  R is eq. (4)
 //     for the stored plane over its own (last-event) window.  R_hat is eq. (7)
@@ -501,6 +517,68 @@ int orc_explicit(const orc_clip* c, const orc_params* p, int new_window, int t_r
   out[2] = cur.mean;
   out[3] = explicit_change(cl, p, new_window, t_ref, t, py, px, theta, &dR);
   return 0;
+}
+
+// Delta-method variance of y = log(E + eps) for the mean E of spp samples with
+// unbiased sample variance var: Var[E_mean] = var / spp, dy/dE = 1 / (E + eps).
+void orc_log_variance(const float* E, const float* var, int spp, double* vy, int64_t n, double eps) {
+  for (int64_t i = 0; i < n; ++i) {
+    const double e = static_cast<double>(E[i]) + eps;
+    vy[i] = static_cast<double>(var[i]) / spp / (e * e);
+  }
+}
+
+// Bandwidth-optimised regressions at items (t * H * W + pixel): for each of the
+// K candidate global bandwidths hs[k] (replacing p->h in eq. (5)) the
+// regression of eqs. (3)-(5), v = A^{-1} e_0 and
+//   SURE_k = (alpha_k - y_c)^2 + 2 vy_c v_0 / W_k - vy_c
+// with vy ([T][H][W]) the MC variance of y.  Outputs per item: theta[n][P] and
+// hsel[n] of the smallest SURE (the first of equal ones), and, nullable,
+// alpha_k[n][K] and sure[n][K] of every candidate.  Returns the number of
+// failed solves (their SURE is +inf).
+int orc_regress_bandwidth(const orc_clip* c, const orc_params* p, const double* hs, int K,
+                          const double* vy, const int64_t* items, int64_t n, double* theta, double* hsel,
+                          double* alpha_k, double* sure_k, int nthreads) {
+  Clip cl{c};
+  const int P = c->F + 3;
+  const int64_t HW = static_cast<int64_t>(c->W) * c->H;
+  int fails = 0;
+#pragma omp parallel for schedule(dynamic, 16) num_threads(nthreads_or_default(nthreads)) reduction(+ : fails)
+  for (int64_t i = 0; i < n; ++i) {
+    const int t = static_cast<int>(items[i] / HW);
+    const int pix = static_cast<int>(items[i] % HW);
+    const double yc = cl.y(t, pix / c->W, pix % c->W);
+    const double s2 = vy[static_cast<int64_t>(t) * HW + pix];
+    double best = INFINITY;
+    int kbest = 0;
+    std::vector<double> th_best(P, NAN);
+    for (int k = 0; k < K; ++k) {
+      orc_params pk = *p;
+      pk.h = hs[k];
+      Fit fit = regress(cl, &pk, t, pix / c->W, pix % c->W, false, false);
+      double sure = INFINITY;
+      std::vector<double> L;
+      if (fit.ok && cholesky(fit.A, P, L)) {
+        std::vector<double> e0(P, 0.0), v(P);
+        e0[0] = 1.0;
+        chol_solve(L, P, e0.data(), v.data());
+        const double d = fit.theta[0] - yc;
+        sure = d * d + 2.0 * s2 * v[0] / fit.W - s2;
+      } else {
+        ++fails;
+      }
+      if (alpha_k) alpha_k[i * K + k] = fit.theta[0];
+      if (sure_k) sure_k[i * K + k] = sure;
+      if (sure < best) {
+        best = sure;
+        kbest = k;
+        th_best = fit.theta;
+      }
+    }
+    for (int j = 0; j < P; ++j) theta[i * P + j] = th_best[j];
+    hsel[i] = hs[kbest];
+  }
+  return fails;
 }
 
 double orc_cond(const double* A, int P) {
