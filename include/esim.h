@@ -317,6 +317,37 @@ size_t esim_backward_scratch_bytes(esim_plan plan, int64_t n);
 int esim_wlr_backward(esim_plan plan, const int64_t* items, int64_t n, const float* g_alpha,
                       float* g_y, double* g_b, void* scratch, size_t scratch_bytes, void* stream);
 
+/* ---- bandwidth optimisation ---------------------------------------------- */
+
+/* MC variance of the log brightness (Sec. 1.1: y = log E): for the mean E of
+ * spp radiance samples with unbiased sample variance var, the delta method
+ * gives vy[i] = var[i] / spp / (E[i] + eps)^2, elementwise, n values.
+ * Errors: E_INVAL (null pointer, n < 0, spp < 1, eps < 0). */
+int esim_log_variance(const float* E, const float* var, int32_t spp, float* vy, int64_t n, float eps,
+                      void* stream);
+
+/* Bandwidth-optimised regression (Sec. 3, bandwidth optimisation: the
+ * bandwidths of eq. (5) chosen per pixel from the bias and the MC variance).
+ * The paper gives the criterion, not the estimator; here only the global
+ * bandwidth h is chosen, among the K candidates hs[0..K) (host array,
+ * replacing the plan's h), by the smallest Stein's unbiased risk estimate of
+ * alpha's mean squared error:
+ *     SURE(h) = (alpha_h - y_c)^2 + 2 vy_c v_0 / W_h - vy_c,   v = A_h^{-1} e_0,
+ * alpha_h's weight on the centre sample being v_0 / W_h.  The first of equal
+ * values wins; a failed factor never does (its outputs stay NaN if all fail).
+ * Items as in esim_wlr_regress with a frame t >= 0: the work list (item i's
+ * results at index i, *count read on the device and clamped to n_out) or, with
+ * worklist NULL, every pixel (index p, n_out >= H*W).  Outputs: alpha[i];
+ * beta[d * n_out + i] over D (nullable); hsel[i] the chosen h (nullable);
+ * sure[i] its SURE (nullable).  vy: [T][H][W], the variance of y
+ * (esim_log_variance).  Single-clip plans, FP64 Gram; one lane per item, K
+ * window passes per item.
+ * Errors: E_INVAL (K outside 1..8, h <= 0, null pointers, n_out),
+ * E_UNSUPPORTED (several clips). */
+int esim_wlr_regress_bandwidth(esim_plan plan, int32_t t, const int64_t* worklist, const int32_t* count,
+                               int64_t n_out, const float* vy, const double* hs, int32_t K, float* alpha,
+                               float* beta, float* hsel, float* sure, void* stream);
+
 /* ---- event-set comparison ------------------------------------------------ */
 
 /* Nearest same-polarity neighbour distances (Sec. 3, "Quantitative comparison":

@@ -75,6 +75,9 @@ SIGNATURES = {
     "esim_step": (_i32, [_vp, _i32, _i32, _vp, _vp, _vp]),
     "esim_backward_scratch_bytes": (_sz, [_vp, _i64]),
     "esim_wlr_backward": (_i32, [_vp, _vp, _i64, _vp, _vp, _vp, _vp, _sz, _vp]),
+    "esim_log_variance": (_i32, [_vp, _vp, _i32, _vp, _i64, _f32, _vp]),
+    "esim_wlr_regress_bandwidth": (_i32, [_vp, _i32, _vp, _vp, _i64, _vp, _vp, _i32, _vp, _vp, _vp, _vp,
+                                          _vp]),
     "esim_nn_scratch_bytes": (_sz, [_i32, _i32, _i32]),
     "esim_nn_distances": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
@@ -250,6 +253,33 @@ def log_brightness(E: torch.Tensor, eps: float = 1e-3, out: Optional[torch.Tenso
     _check(load().esim_log_brightness(_ptr(E), _ptr(y), E.numel(), eps, _stream(stream)),
            "log_brightness")
     return y
+
+
+def log_variance(E: torch.Tensor, var: torch.Tensor, spp: int, eps: float = 1e-3,
+                 out: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+    """MC variance of y = log(E + eps) for the mean E of spp samples with
+    sample variance var (esim_log_variance)."""
+    for t in (E, var):
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("E and var must be contiguous float32")
+    if var.shape != E.shape:
+        raise ValueError("E and var shapes differ")
+    vy = torch.empty_like(E) if out is None else out
+    _check(load().esim_log_variance(_ptr(E), _ptr(var), int(spp), _ptr(vy), E.numel(), eps,
+                                    _stream(stream)), "log_variance")
+    return vy
+
+
+def regress_bandwidth(plan: Plan, t: int, worklist: Optional[torch.Tensor], count: Optional[torch.Tensor],
+                      n_out: int, vy: torch.Tensor, hs: Sequence[float], alpha: torch.Tensor,
+                      beta: Optional[torch.Tensor] = None, hsel: Optional[torch.Tensor] = None,
+                      sure: Optional[torch.Tensor] = None, stream=None):
+    """Bandwidth-optimised regression at frame t (esim_wlr_regress_bandwidth):
+    the candidate h of hs with the smallest SURE, per item."""
+    arr = (ctypes.c_double * len(hs))(*[float(h) for h in hs])
+    _check(load().esim_wlr_regress_bandwidth(plan.h, t, _ptr(worklist), _ptr(count), n_out, _ptr(vy), arr,
+                                             len(hs), _ptr(alpha), _ptr(beta), _ptr(hsel), _ptr(sure),
+                                             _stream(stream)), "wlr_regress_bandwidth")
 
 
 def threshold(plan: Plan, t: int, dl: torch.Tensor, worklist: torch.Tensor, count: torch.Tensor,

@@ -17,7 +17,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libesim.so")
 SOURCES = ["esim_api.hip", "esim_compact.hip", "esim_regress.hip", "esim_backward.hip", "esim_metrics.hip",
-           "esim_explicit.hip"]
+           "esim_explicit.hip", "esim_bandwidth.hip"]
 # the regression kernels of feature count f are compiled from esim_regress_inst.hip
 # with -DESIM_REGRESS_F=f, one object each, so that they build in parallel
 REGRESS_F = range(1, 13)

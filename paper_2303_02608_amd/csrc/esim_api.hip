@@ -8,6 +8,7 @@
 #include <vector>
 
 #include "esim.h"
+#include "esim_bandwidth.h"
 #include "esim_compact.h"
 #include "esim_internal.h"
 
@@ -566,6 +567,57 @@ int esim_step(esim_plan pl, int32_t t, int32_t mode, float* dl, esim_events_buf*
                                                  nullptr, pl->ws, nullptr, nullptr, &ed, s),
                        "step(raw)");
     return fail(ESIM_E_INVAL, "bad mode");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+int esim_log_variance(const float* E, const float* var, int32_t spp, float* vy, int64_t n, float eps,
+                      void* stream) {
+  try {
+    if (n < 0 || spp < 1 || !(eps >= 0)) return fail(ESIM_E_INVAL, "n < 0, spp < 1 or eps < 0");
+    if (n == 0) return ok();
+    if (!E || !var || !vy) return fail(ESIM_E_INVAL, "null pointer");
+    return hip_check(esim::launch_log_variance(E, var, vy, n, spp, eps, static_cast<hipStream_t>(stream)),
+                     "log_variance");
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+int esim_wlr_regress_bandwidth(esim_plan pl, int32_t t, const int64_t* worklist, const int32_t* count,
+                               int64_t n_out, const float* vy, const double* hs, int32_t K, float* alpha,
+                               float* beta, float* hsel, float* sure, void* stream) {
+  try {
+    if (!pl || !alpha || !vy || !hs) return fail(ESIM_E_INVAL, "null argument");
+    if (pl->nclips != 1) return fail(ESIM_E_UNSUPPORTED, "bandwidth optimisation takes single-clip plans");
+    const esim::ClipDev& hc = pl->host[0];
+    if (t < 0 || t >= hc.T) return fail(ESIM_E_INVAL, "t outside the clip");
+    if (K < 1 || K > esim::kMaxBandwidths) return fail(ESIM_E_INVAL, "K outside 1..8");
+    if (worklist && !count) return fail(ESIM_E_INVAL, "worklist without count");
+    if (!worklist && n_out < pl->npix) return fail(ESIM_E_INVAL, "n_out < plan pixels");
+    if (n_out < 1) return fail(ESIM_E_INVAL, "n_out < 1");
+    esim::BandwidthArgs a{};
+    for (int k = 0; k < K; ++k) {
+      if (!(hs[k] > 0) || std::isinf(hs[k])) return fail(ESIM_E_INVAL, "bandwidths must be positive and finite");
+      a.h[k] = hs[k];
+      a.scale[k] = hc.h / hs[k];
+    }
+    a.clip = pl->dev;
+    a.t = t;
+    a.items = worklist;
+    a.count = count;
+    a.n_out = n_out;
+    a.vy = vy;
+    a.K = K;
+    a.alpha = alpha;
+    a.beta = beta;
+    a.hsel = hsel;
+    a.sure = sure;
+    return hip_check(esim::launch_bandwidth(a, pl->F, pl->f16, worklist ? std::min(n_out, pl->wl_capacity)
+                                                                         : pl->npix,
+                                            static_cast<hipStream_t>(stream)),
+                     "regress_bandwidth");
   } catch (...) {
     return fail(ESIM_E_HIP, "exception");
   }

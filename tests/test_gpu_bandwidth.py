@@ -1,0 +1,157 @@
+"""Bandwidth-optimised regression (per-item h from candidates by SURE with the
+MC variance) on the GPU against the oracle.
+
+Tolerances: alpha and beta of the chosen candidate as for every regression
+(1e-4 max(1, |.|)).  The choice itself is an argmin over SURE values that the
+two sides compute from the same definition in different precision (FP32
+weights and variance input on the GPU): where the GPU takes another candidate
+than the oracle, the oracle's own SURE at the GPU's choice must lie within
+1e-5 + 1e-4 |SURE_min| of its minimum (an alpha error delta moves SURE by
+about 2 |alpha - y_c| delta), and such flips must stay rare."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2303_02608_amd import binding as B
+from paper_2303_02608_amd import synth
+from parity_util import say
+
+pytestmark = pytest.mark.gpu
+
+HS = [0.5, 0.75, 1.0, 1.5, 2.0]
+
+
+@pytest.fixture(scope="module")
+def clip():
+    cfg = synth.config_spec(0)
+    d = synth.make_clip(cfg["spec"])
+    return dict(cfg=cfg, E=d["E"].numpy(), var=d["var"].numpy(), feat=d["feat"].numpy(),
+                spp=cfg["spec"].spp)
+
+
+def _gpu(clip, p, t, items=None, hs=HS):
+    E = torch.from_numpy(clip["E"]).cuda()
+    var = torch.from_numpy(clip["var"]).cuda()
+    feat = torch.from_numpy(clip["feat"]).cuda()
+    y = B.log_brightness(E)
+    vy = B.log_variance(E, var, clip["spp"])
+    plan = B.Plan([y], [feat], [p])
+    T, F, H, W = feat.shape
+    n = H * W if items is None else len(items)
+    a = torch.empty(n, device="cuda")
+    b = torch.empty((F + 2, n), device="cuda")
+    h = torch.empty(n, device="cuda")
+    s = torch.empty(n, device="cuda")
+    if items is None:
+        B.regress_bandwidth(plan, t, None, None, n, vy, hs, a, b, h, s)
+    else:
+        wl = torch.from_numpy(np.asarray(items, np.int64)).cuda()
+        cnt = torch.tensor([n, n], dtype=torch.int32, device="cuda")
+        B.regress_bandwidth(plan, t, wl, cnt, n, vy, hs, a, b, h, s)
+    torch.cuda.synchronize()
+    return dict(alpha=a.cpu().numpy(), beta=b.cpu().numpy(), h=h.cpu().numpy(), sure=s.cpu().numpy(),
+                vy=vy.cpu().numpy(), plan=plan, y=y, feat=feat)
+
+
+def _oracle(clip, p, t, pix, hs=HS):
+    oc = oracle.Clip(oracle.log_brightness(clip["E"]), clip["feat"])
+    vy = oracle.log_variance(clip["E"], clip["var"], clip["spp"])
+    T, F, H, W = clip["feat"].shape
+    return oracle.regress_bandwidth(oc, oracle.Params(p.r, p.tr, p.C, p.h, p.b, p.ridge), np.asarray(hs),
+                                    vy, t * H * W + np.asarray(pix, np.int64)), vy
+
+
+def _compare(g, o, pix, hs=HS):
+    hs = np.asarray(hs)
+    kg = np.searchsorted(hs, g["h"])
+    assert np.all(hs[kg] == g["h"]), "the GPU's h is a candidate"
+    sm = o["sure"].min(axis=1)
+    rows = np.arange(len(pix))
+    so = o["sure"][rows, kg]
+    flips = kg != np.argmin(o["sure"], axis=1)
+    assert np.all(so - sm <= 1e-5 + 1e-4 * np.abs(sm)), np.max(so - sm)
+    assert flips.mean() <= 0.01, flips.mean()
+    # alpha and SURE of the GPU's choice against the oracle's same candidate
+    ao = o["alpha_k"][rows, kg]
+    assert np.max(np.abs(g["alpha"] - ao) / np.maximum(1, np.abs(ao))) <= 1e-4
+    assert np.max(np.abs(g["sure"] - so) / np.maximum(1e-3, np.abs(so))) <= 1e-3
+    # beta where the choices agree (the oracle only reports the chosen theta)
+    same = ~flips
+    bo = o["theta"][same, 1:]
+    bg = g["beta"].T[same]
+    assert np.max(np.abs(bg - bo) / np.maximum(1, np.abs(bo))) <= 1e-4
+    return flips.sum()
+
+
+def test_log_variance_matches_oracle(clip):
+    say("log variance")
+    E = torch.from_numpy(clip["E"]).cuda()
+    var = torch.from_numpy(clip["var"]).cuda()
+    vy = B.log_variance(E, var, clip["spp"]).cpu().numpy()
+    ref = oracle.log_variance(clip["E"], clip["var"], clip["spp"])
+    assert np.allclose(vy, ref, rtol=2e-6, atol=0)
+
+
+@pytest.mark.parametrize("t,tr", [(0, 0), (7, 1), (15, 1)])
+def test_dense_bandwidth_regression_matches_oracle(clip, t, tr):
+    cfg = clip["cfg"]
+    p = B.Params(r=cfg["r"], tr=tr, C=cfg["C"])
+    say(f"dense bandwidth regression t={t} tr={tr}")
+    g = _gpu(clip, p, t)
+    H, W = clip["feat"].shape[2:]
+    pix = np.arange(H * W)
+    o, _ = _oracle(clip, p, t, pix)
+    nflip = _compare(g, o, pix)
+    share = [float(np.mean(g["h"] == h)) for h in HS]
+    say(f"t={t}: chosen-h shares {share}, choices differing from the oracle {nflip}")
+    assert max(share) < 1.0          # the choice varies over the image
+
+
+def test_work_list_equals_dense(clip):
+    cfg = clip["cfg"]
+    p = B.Params(r=cfg["r"], tr=1, C=cfg["C"])
+    say("bandwidth regression: work list vs dense")
+    H, W = clip["feat"].shape[2:]
+    d = _gpu(clip, p, 5)
+    rng = np.random.default_rng(2)
+    pix = np.sort(rng.choice(H * W, 700, replace=False))
+    g = _gpu(clip, p, 5, items=pix)
+    for k in ("alpha", "h", "sure"):
+        assert np.array_equal(g[k], d[k][pix]), k
+    assert np.array_equal(g["beta"], d["beta"][:, pix])
+
+
+def test_single_candidate_is_the_plain_regression(clip):
+    """With the plan's own h as the only candidate, the outputs are those of
+    the ordinary regression."""
+    cfg = clip["cfg"]
+    p = B.Params(r=cfg["r"], tr=1, C=cfg["C"])
+    say("bandwidth regression with one candidate")
+    g = _gpu(clip, p, 3, hs=[1.0])
+    H, W = clip["feat"].shape[2:]
+    a = torch.empty(H * W, device="cuda")
+    b = torch.empty((clip["feat"].shape[1] + 2, H * W), device="cuda")
+    B.regress(g["plan"], 3, None, None, H * W, a, b)
+    torch.cuda.synchronize()
+    assert np.all(g["h"] == 1.0)
+    assert np.allclose(g["alpha"], a.cpu().numpy(), rtol=1e-6, atol=1e-6)
+    assert np.allclose(g["beta"], b.cpu().numpy(), rtol=1e-5, atol=1e-5)
+
+
+def test_bandwidth_validation(clip):
+    cfg = clip["cfg"]
+    p = B.Params(r=cfg["r"], tr=0, C=cfg["C"])
+    say("bandwidth regression validation")
+    g = _gpu(clip, p, 0, hs=[1.0])
+    vy = torch.from_numpy(g["vy"]).cuda()
+    H, W = clip["feat"].shape[2:]
+    a = torch.empty(H * W, device="cuda")
+    for hs in ([], [1.0] * 9, [1.0, 0.0], [1.0, float("inf")]):
+        with pytest.raises(B.EsimError):
+            B.regress_bandwidth(g["plan"], 0, None, None, H * W, vy, hs, a)
+    with pytest.raises(B.EsimError):
+        B.regress_bandwidth(g["plan"], clip["feat"].shape[0], None, None, H * W, vy, [1.0], a)
+    two = B.Plan([g["y"], g["y"]], [g["feat"], g["feat"]], [p, p])
+    with pytest.raises(B.EsimError):
+        B.regress_bandwidth(two, 0, None, None, 2 * H * W, vy, [1.0], torch.empty(2 * H * W, device="cuda"))
