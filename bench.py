@@ -24,7 +24,9 @@ the noise-free frames: precision, recall, F1 and Chamfer distance over a sweep
 of C, with the conversion times), `threshold` (the closed form of Prop. 1
 against the explicit Delta R sums over the last-event window and over the
 current frame's window: times, events and quality, on the clip and under a
-global illumination flicker).
+global illumination flicker), `bandwidth` (WLR+ESIM and the thresholded method
+with the regression bandwidth chosen per regression by SURE from the MC
+variance, against the plain regressions).
 
 Roofline: the dominant kernel is the regression.  Its launches are bracketed
 with HIP events on the launch stream during an instrumented eager pass of the
@@ -405,6 +407,97 @@ def workload_threshold(args, B, synth, Simulator):
     return out
 
 
+def workload_bandwidth(args, B, synth, Simulator):
+    """Bandwidth optimisation (Sec. 3): the DVS clip converted by WLR+ESIM and by
+    the thresholded method with the regression's global bandwidth h chosen per
+    regression among HS by SURE with the MC variance, against the plain
+    regressions (h = 1): times, the chosen-h shares, and event quality against
+    ESIM on the noise-free frames."""
+    import torch
+    from paper_2303_02608_amd import quality as Q
+    cfg = synth.config_spec(1)
+    spec = cfg["spec"]
+    HS = [0.5, 0.75, 1.0, 1.5, 2.0]
+    t0 = time.time()
+    d = synth.make_clip(spec, device="cuda", reference=True)
+    feat = d["feat"]
+    T, F, H, W = feat.shape
+    HW = H * W
+    r, tr, C = cfg["r"], cfg["tr"], cfg["C"]
+    y = B.log_brightness(d["E"])
+    vy = B.log_variance(d["E"], d["var"], spec.spp)
+    yref = B.log_brightness(d["E_ref"])
+    log(f"generated {W}x{H}x{T} with variance and reference frames in {time.time() - t0:.1f}s")
+    p = B.Params(r=r, tr=tr, C=C)
+    refd = Q.to_device(Simulator(yref, feat, p).run("raw"))
+    taus, rmax = [5e-4, 2e-3, 5e-3, 1e-2], 0.05
+    sim = Simulator(y, feat, p)
+    plan, n = sim.plan, HW
+    hsel = torch.empty(HW, device="cuda")
+    counts = torch.zeros((T, len(HS)), dtype=torch.int64, device="cuda")
+    hs_t = torch.tensor(HS, device="cuda")
+
+    def exhaustive_bw():
+        sim.ev.count.zero_()
+        for t in range(T):
+            B.regress_bandwidth(plan, t, None, None, n, vy, HS, sim.alpha, None, hsel)
+            B.events(plan, t, B.EXHAUSTIVE, sim.ev, dl=sim.dl, alpha=sim.alpha, n_out=n)
+
+    def thresholded_bw():
+        sim.ev.count.zero_()
+        B.regress_bandwidth(plan, 0, None, None, n, vy, HS, sim.alpha, sim.beta, hsel)
+        B.events(plan, 0, B.INIT, None, alpha=sim.alpha, beta=sim.beta, n_out=n)
+        for t in range(1, T):
+            B.threshold(plan, t, sim.dl, sim.worklist, sim.count)
+            B.regress_bandwidth(plan, t, sim.worklist, sim.count, n, vy, HS, sim.alpha, sim.beta)
+            B.events(plan, t, B.THRESHOLDED, sim.ev, worklist=sim.worklist, count=sim.count, dl=sim.dl,
+                     alpha=sim.alpha, beta=sim.beta, n_out=n)
+
+    out = {"workload": f"bandwidth optimisation, DVS {W}x{H}x{T}, F={F} f32, r={r}, tr={tr}, C={C}; "
+                       f"candidates h = {HS} chosen by SURE with the MC variance; reference = ESIM on "
+                       f"the noise-free frames", "taus": taus, "rmax": rmax}
+    runs = {"exhaustive_plain": lambda: sim.enqueue("exhaustive"),
+            "exhaustive_bandwidth": exhaustive_bw,
+            "thresholded_plain": lambda: sim.enqueue("thresholded"),
+            "thresholded_bandwidth": thresholded_bw}
+    for name, fn in runs.items():
+        run = _graph(fn)
+        ms = _time_ms(run, max(1, args.steps))
+        ev = sim.events()
+        m = Q.metrics(Q.to_device(ev), refd, W, H, T, taus, rmax)
+        out[name] = {"ms": round(ms, 3), "pixel_frames_per_s": round(T * HW / (ms * 1e-3), 1),
+                     "events": ev["count"], "P": [round(v, 4) for v in m["P"]],
+                     "R": [round(v, 4) for v in m["R"]], "F": [round(v, 4) for v in m["F"]], "CD": m["CD"]}
+        log(f"{name}: {ms:.2f} ms, {ev['count']} events, F {out[name]['F']}")
+        del run
+    # the dense bandwidth launch alone, with the chosen-h shares over the clip
+    stream = torch.cuda.current_stream()
+    marks = []
+    for t in range(T):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        B.regress_bandwidth(plan, t, None, None, n, vy, HS, sim.alpha, None, hsel)
+        e1.record(stream)
+        marks.append((e0, e1))
+        counts[t] = (hsel[:, None] == hs_t[None, :]).sum(dim=0)
+    torch.cuda.synchronize()
+    dms = np.array([a.elapsed_time(b) for a, b in marks])
+    fl = 0.0
+    xs, ys = np.arange(HW) % W, np.arange(HW) // W
+    for t in range(T):
+        fl += len(HS) * regress_flops(omega_sizes(xs, ys, np.full(HW, t), W, H, T, r, tr), F).sum()
+    ach = fl / (dms.sum() * 1e-3) / 1e12
+    share = (counts.sum(dim=0).double() / (T * HW)).cpu().numpy()
+    out["dense_launch"] = {"kernel": f"bandwidth_kernel<F={F},f32>", "candidates": len(HS),
+                           "avg_ms": round(float(dms.mean()), 4),
+                           "roofline": {"bound": "alu", "achieved": round(ach, 3), "peak": PEAK_ALU_TFLOPS,
+                                        "unit": "TFLOP/s", "frac": round(ach / PEAK_ALU_TFLOPS, 4),
+                                        "flop_model": "candidates x F_reg per regression"},
+                           "chosen_h_share": {str(h): round(float(v), 4) for h, v in zip(HS, share)}}
+    log(f"dense bandwidth launch avg {dms.mean():.3f} ms ({ach:.1f} TFLOP/s); h shares {share}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -422,7 +515,8 @@ def main():
                     help="load the clip saved by --save-clip instead of generating it")
     ap.add_argument("--schedule", type=str, default=None,
                     help="lanes_dense,lanes_list,blocks_per_cu (skips the autotuner)")
-    ap.add_argument("--workload", choices=("dvs", "precision", "batch", "diff", "quality", "threshold"),
+    ap.add_argument("--workload", choices=("dvs", "precision", "batch", "diff", "quality", "threshold",
+                                           "bandwidth"),
                     default="dvs",
                     help="dvs (default, the contract line) or one of the extension workloads")
     ap.add_argument("--copy-probe", action="store_true",
@@ -450,7 +544,8 @@ def main():
     torch.cuda.set_device(dev)
     if args.workload != "dvs":
         fn = {"precision": workload_precision, "batch": workload_batch, "diff": workload_diff,
-              "quality": workload_quality, "threshold": workload_threshold}
+              "quality": workload_quality, "threshold": workload_threshold,
+              "bandwidth": workload_bandwidth}
         res = fn[args.workload](args, B, synth, Simulator)
         res = {"metric": f"{args.workload} workload", "n_gpus": 1, "dtype": "f64",
                "data": "synthetic", **res}

@@ -83,6 +83,44 @@ def test_dvs_explicit_thresholds_on_sampled_pixels(dvs, form):
     assert orc["count"] > 0
 
 
+def test_dvs_bandwidth_regression_on_sampled_pixels():
+    """The bandwidth-optimised regression on a frame of the DVS clip (dense
+    launch, as the bandwidth workload runs it) against the oracle on sampled
+    pixels; the choice band as in the small-workload test."""
+    cfg = synth.config_spec(1)
+    say("DVS bandwidth regression, frame 57")
+    d = synth.make_clip(cfg["spec"], device="cuda", frames=range(55, 60))
+    E, var, feat = d["E"], d["var"], d["feat"]
+    y = B.log_brightness(E)
+    vy = B.log_variance(E, var, cfg["spec"].spp)
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"])
+    plan = B.Plan([y], [feat], [p])
+    HW = plan.npix
+    hs = [0.5, 0.75, 1.0, 1.5, 2.0]
+    a = torch.empty(HW, device="cuda")
+    h = torch.empty(HW, device="cuda")
+    s = torch.empty(HW, device="cuda")
+    B.regress_bandwidth(plan, 2, None, None, HW, vy, hs, a, None, h, s)
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(5)
+    pix = rng.choice(HW, 300, replace=False)
+    En, vn = E.cpu().numpy(), var.cpu().numpy()
+    oc = oracle.Clip(oracle.log_brightness(En), feat.cpu().numpy())
+    o = oracle.regress_bandwidth(oc, oracle.Params(p.r, p.tr, p.C), np.array(hs),
+                                 oracle.log_variance(En, vn, cfg["spec"].spp), 2 * HW + pix)
+    hg = h.cpu().numpy()[pix]
+    kg = np.searchsorted(np.array(hs), hg)
+    rows = np.arange(pix.size)
+    sm = o["sure"].min(axis=1)
+    so = o["sure"][rows, kg]
+    flips = int(np.sum(kg != np.argmin(o["sure"], axis=1)))
+    say(f"DVS bandwidth: {flips} of {pix.size} choices differ from the oracle's")
+    assert np.all(so - sm <= 1e-5 + 1e-4 * np.abs(sm))
+    assert flips <= 3
+    ao = o["alpha_k"][rows, kg]
+    assert np.max(np.abs(a.cpu().numpy()[pix] - ao) / np.maximum(1, np.abs(ao))) <= 1e-4
+
+
 def test_dvs_sampled_regressions(dvs):
     cfg = dvs["cfg"]
     p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"])
