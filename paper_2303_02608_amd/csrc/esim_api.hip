@@ -616,7 +616,7 @@ int esim_wlr_regress_bandwidth(esim_plan pl, int32_t t, const int64_t* worklist,
     a.sure = sure;
     return hip_check(esim::launch_bandwidth(a, pl->F, pl->f16, worklist ? std::min(n_out, pl->wl_capacity)
                                                                          : pl->npix,
-                                            static_cast<hipStream_t>(stream)),
+                                            hc.r, static_cast<hipStream_t>(stream)),
                      "regress_bandwidth");
   } catch (...) {
     return fail(ESIM_E_HIP, "exception");

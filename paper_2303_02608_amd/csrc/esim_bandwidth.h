@@ -25,6 +25,6 @@ struct BandwidthArgs {
 
 hipError_t launch_log_variance(const float* E, const float* var, float* vy, int64_t n, int spp, float eps,
                                hipStream_t s);
-hipError_t launch_bandwidth(const BandwidthArgs& a, int F, bool f16, int64_t max_items, hipStream_t s);
+hipError_t launch_bandwidth(const BandwidthArgs& a, int F, bool f16, int64_t max_items, int r, hipStream_t s);
 
 }  // namespace esim

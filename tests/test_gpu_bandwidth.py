@@ -108,18 +108,25 @@ def test_dense_bandwidth_regression_matches_oracle(clip, t, tr):
     assert max(share) < 1.0          # the choice varies over the image
 
 
-def test_work_list_equals_dense(clip):
+@pytest.mark.parametrize("r", [5, 8])
+def test_work_list_matches_oracle_and_dense(clip, r):
+    """Work lists run 16 lanes per item (one column each at r = 5; two column
+    passes at r = 8): parity with the oracle, and the dense launch's results
+    at the same pixels to summation-order rounding."""
     cfg = clip["cfg"]
-    p = B.Params(r=cfg["r"], tr=1, C=cfg["C"])
-    say("bandwidth regression: work list vs dense")
+    p = B.Params(r=r, tr=1, C=cfg["C"])
+    say(f"bandwidth regression: work list r={r}")
     H, W = clip["feat"].shape[2:]
-    d = _gpu(clip, p, 5)
     rng = np.random.default_rng(2)
     pix = np.sort(rng.choice(H * W, 700, replace=False))
     g = _gpu(clip, p, 5, items=pix)
-    for k in ("alpha", "h", "sure"):
-        assert np.array_equal(g[k], d[k][pix]), k
-    assert np.array_equal(g["beta"], d["beta"][:, pix])
+    o, _ = _oracle(clip, p, 5, pix)
+    nflip = _compare(g, o, pix)
+    d = _gpu(clip, p, 5)
+    same = g["h"] == d["h"][pix]
+    say(f"r={r}: {nflip} choices differ from the oracle, {np.sum(~same)} from the dense launch")
+    assert np.mean(same) >= 0.99
+    assert np.allclose(g["alpha"][same], d["alpha"][pix][same], rtol=1e-5, atol=1e-5)
 
 
 def test_single_candidate_is_the_plain_regression(clip):
