@@ -56,6 +56,12 @@ def test_invalid_arguments_fail_before_any_launch(lib):
     assert lib.esim_wlr_regress(None, 0, None, None, 0, None, None, None, None, None) == B.E_INVAL
     assert lib.esim_events(None, 0, 1, None, None, None, None, None, 0, None, None) == B.E_INVAL
     assert lib.esim_wlr_backward(None, None, 1, None, None, None, None, 0, None) == B.E_INVAL
+    assert lib.esim_log_variance(None, None, 4, None, 10, 1e-3, None) == B.E_INVAL
+    assert lib.esim_log_variance(None, None, 0, None, 0, 1e-3, None) == B.E_INVAL    # spp < 1
+    assert lib.esim_log_variance(None, None, 4, None, 0, 1e-3, None) == B.OK
+    hs = (ctypes.c_double * 1)(1.0)
+    assert lib.esim_wlr_regress_bandwidth(None, 0, None, None, 1, None, hs, 1, None, None, None, None,
+                                          None) == B.E_INVAL
     assert lib.esim_plan_pixels(None) == -1
     assert lib.esim_plan_set_schedule(None, 4, 16, 4) == B.E_INVAL
 
