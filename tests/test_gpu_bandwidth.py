@@ -162,3 +162,24 @@ def test_bandwidth_validation(clip):
     two = B.Plan([g["y"], g["y"]], [g["feat"], g["feat"]], [p, p])
     with pytest.raises(B.EsimError):
         B.regress_bandwidth(two, 0, None, None, 2 * H * W, vy, [1.0], torch.empty(2 * H * W, device="cuda"))
+
+
+@pytest.mark.parametrize("F,feat_dtype,r", [(1, "f32", 4), (12, "f32", 3), (7, "f16", 5)])
+def test_bandwidth_feature_counts_and_f16(F, feat_dtype, r):
+    """Other instances: the extreme feature counts and FP16 features (the
+    oracle decodes the same FP16 bits), dense and work list."""
+    W, H, T = 40, 36, 4
+    d = synth.random_features_clip(W, H, T, F, seed=80 + F, feat_dtype=feat_dtype)
+    rng = np.random.default_rng(F)
+    var = (d["E"].numpy() ** 2 * rng.uniform(0.2, 2.0, size=(T, H, W))).astype(np.float32)
+    clip = dict(E=d["E"].numpy(), var=var, feat=d["feat"].numpy(), spp=4)
+    p = B.Params(r=r, tr=1, C=0.1)
+    say(f"bandwidth regression F={F} {feat_dtype} r={r}")
+    pix = np.arange(H * W)
+    g = _gpu(clip, p, 2)
+    o, _ = _oracle(clip, p, 2, pix)
+    _compare(g, o, pix)
+    sel = np.sort(rng.choice(H * W, 300, replace=False))
+    gl = _gpu(clip, p, 2, items=sel)
+    ol, _ = _oracle(clip, p, 2, sel)
+    _compare(gl, ol, sel)

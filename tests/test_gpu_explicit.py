@@ -221,3 +221,27 @@ def test_explicit_with_compensated_fp32_regression(small_clip, form):
         assert np.array_equal(ea[k], eb[k]), k
     assert torch.equal(a.state.rmom, b.state.rmom)
     assert torch.isfinite(a.state.rmom).all()
+
+
+def test_explicit_batch_graph_replay():
+    """A batched plan with the current-window form captured in a graph: every
+    replay reproduces the eager run."""
+    from paper_2303_02608_amd.simulator import BatchSimulator
+    say("explicit new-window batch graph replay")
+    clips = []
+    for i, (W, H, T, r) in enumerate([(40, 30, 7, 3), (33, 41, 5, 4), (48, 24, 6, 2)]):
+        spec = synth.ClipSpec(W=W, H=H, T=T, spp=3, F=7, n_discs=3, speed=(0.5, 2.0), seed=6100 + i)
+        d = synth.make_clip(spec)
+        y, fd = to_dev(d["E"].numpy(), d["feat"].numpy())
+        clips.append((y, fd, B.Params(r=r, tr=1, C=0.2, threshold=B.THRESHOLD_NEW_WINDOW)))
+    bs = BatchSimulator([c[0] for c in clips], [c[1] for c in clips], [c[2] for c in clips])
+    eager = bs.run()
+    assert eager["count"] > 0
+    bs.capture()
+    for _ in range(3):
+        bs.graph.replay()
+        torch.cuda.synchronize()
+        got = bs.ev.host()
+        for k in ("x", "y", "t", "p", "clip"):
+            assert np.array_equal(got[k], eager[k]), k
+        _ = (clips[0][0] * 2).sum().item()
