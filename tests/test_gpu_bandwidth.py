@@ -64,8 +64,9 @@ def _oracle(clip, p, t, pix, hs=HS):
 
 def _compare(g, o, pix, hs=HS):
     hs = np.asarray(hs)
-    kg = np.searchsorted(hs, g["h"])
-    assert np.all(hs[kg] == g["h"]), "the GPU's h is a candidate"
+    # the GPU reports h in FP32: the nearest candidate, within FP32 rounding
+    kg = np.argmin(np.abs(hs[None, :] - g["h"].astype(np.float64)[:, None]), axis=1)
+    assert np.all(np.abs(hs[kg] - g["h"]) <= 1e-6 * hs[kg]), "the GPU's h is a candidate"
     sm = o["sure"].min(axis=1)
     rows = np.arange(len(pix))
     so = o["sure"][rows, kg]
@@ -183,3 +184,19 @@ def test_bandwidth_feature_counts_and_f16(F, feat_dtype, r):
     gl = _gpu(clip, p, 2, items=sel)
     ol, _ = _oracle(clip, p, 2, sel)
     _compare(gl, ol, sel)
+
+
+def test_eight_candidates(clip):
+    """The largest candidate set (8 bandwidths, unsorted)."""
+    cfg = clip["cfg"]
+    p = B.Params(r=cfg["r"], tr=1, C=cfg["C"])
+    hs = [1.0, 0.4, 2.5, 0.7, 1.8, 0.55, 1.25, 3.2]
+    say("bandwidth regression with 8 candidates")
+    g = _gpu(clip, p, 4, hs=hs)
+    H, W = clip["feat"].shape[2:]
+    pix = np.arange(H * W)
+    o, _ = _oracle(clip, p, 4, pix, hs=hs)
+    order = np.argsort(hs)
+    hs_sorted = np.asarray(hs)[order]
+    o_sorted = dict(o, sure=o["sure"][:, order], alpha_k=o["alpha_k"][:, order])
+    _compare(g, o_sorted, pix, hs=hs_sorted)
