@@ -525,8 +525,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU; the path shards by pixel rows across GPUs "
-              "only on paper (see DESIGN.md).  Run with --gpus 1.", file=sys.stderr)
+        print("bench.py runs on one GPU: sharding the clip by pixel rows across GPUs is designed "
+              "but not implemented.  Run with --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -21,9 +21,10 @@
 // Precision.  The weight exponent is summed in FP64 from FP64 differences of
 // the FP32 inputs and exponentiated with the FP32 hardware exp2 (about 1e-7
 // relative).  Gram, right-hand side and Cholesky are FP64: without packed FP32
-// (disabled in this build) an FP64 FMA issues at the same rate as an FP32 one
-// on CDNA4, and the windows are ill-conditioned (kappa up to ~1e6 with a
-// 1e-6 ridge), which FP32 accumulation does not survive at the 1e-4 contract.
+// (disabled by the compile flags) an FP64 FMA issues at the same rate as an
+// FP32 one on CDNA4, and the windows are ill-conditioned (kappa up to ~1e6
+// with a 1e-6 ridge), which FP32 accumulation does not survive at the 1e-4
+// contract.
 //
 // After the window loop the L lane partials are summed with DPP, every lane of
 // the item factors the (F+3)x(F+3) system redundantly (registers only) and the
