@@ -205,19 +205,38 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
     __syncthreads();
     if (k + 1 < nrow) load_map(k + 1, nxt);
     // each wave walks the present items of its 64-column chunks (a
-    // wave-uniform loop over the ballot); lanes m < span load the item's
-    // slots m, one coalesced 4 (2r + 1)-byte read per item
+    // wave-uniform loop over the ballot); the lanes load the items' slots,
+    // coalesced 4 (2r + 1)-byte reads: four items per step for windows of at
+    // most 16 columns, one otherwise
     const int64_t sbase = static_cast<int64_t>((tq - tc + tr) * span + (yq - yc + r)) * span;
     for (int base = wave * kWave; base < seg; base += kGatherTile) {
       const int c = base + lane;
       const int32_t it = c < seg ? mrow[c] : -1;
       uint64_t mask = __ballot(it >= 0);
-      while (mask != 0) {
-        const int bit = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-        mask &= mask - 1;
-        const int32_t itc = __shfl(it, bit);
-        for (int m = lane; m < span; m += kWave)
-          cx[(base + bit) * span + m] = bd.contrib[static_cast<int64_t>(itc) * bd.S + sbase + m];
+      if (span <= 16) {
+        // four items per step, 16 lanes each (lane q * 16 + m takes slot m of
+        // the q-th next item)
+        const int q = lane >> 4, m = lane & 15;
+        while (mask != 0) {
+          int bits[4];
+#pragma unroll
+          for (int u = 0; u < 4; ++u) {
+            bits[u] = mask != 0 ? __ffsll(static_cast<unsigned long long>(mask)) - 1 : -1;
+            if (mask != 0) mask &= mask - 1;
+          }
+          const int bq = q == 0 ? bits[0] : q == 1 ? bits[1] : q == 2 ? bits[2] : bits[3];
+          const int32_t itc = __shfl(it, bq < 0 ? 0 : bq);
+          if (bq >= 0 && m < span)
+            cx[(base + bq) * span + m] = bd.contrib[static_cast<int64_t>(itc) * bd.S + sbase + m];
+        }
+      } else {
+        while (mask != 0) {
+          const int bit = __ffsll(static_cast<unsigned long long>(mask)) - 1;
+          mask &= mask - 1;
+          const int32_t itc = __shfl(it, bit);
+          for (int mm = lane; mm < span; mm += kWave)
+            cx[(base + bit) * span + mm] = bd.contrib[static_cast<int64_t>(itc) * bd.S + sbase + mm];
+        }
       }
     }
     __syncthreads();
