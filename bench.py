@@ -26,7 +26,9 @@ against the explicit Delta R sums over the last-event window and over the
 current frame's window: times, events and quality, on the clip and under a
 global illumination flicker), `bandwidth` (WLR+ESIM and the thresholded method
 with the regression bandwidth chosen per regression by SURE from the MC
-variance, against the plain regressions).
+variance, against the plain regressions), `multicrossing` (raw and WLR+ESIM
+with every crossing against one event per pixel-frame, scored against
+every-crossing ESIM on the noise-free frames, with the comparison's own time).
 
 Roofline: the dominant kernel is the regression.  Its launches are bracketed
 with HIP events on the launch stream during an instrumented eager pass of the
@@ -498,6 +500,55 @@ def workload_bandwidth(args, B, synth, Simulator):
     return out
 
 
+def workload_multicrossing(args, B, synth, Simulator):
+    """Every-crossing ESIM (the multi_crossing option) on the DVS clip: raw and
+    WLR+ESIM conversions with one event per pixel-frame and with every
+    crossing, their times, and their quality against every-crossing ESIM on the
+    noise-free frames; plus the event-set comparison's own time (the GPU
+    nearest-neighbour search of both directions)."""
+    import torch
+    from paper_2303_02608_amd import quality as Q
+    cfg = synth.config_spec(1)
+    spec = cfg["spec"]
+    t0 = time.time()
+    d = synth.make_clip(spec, device="cuda", reference=True)
+    feat = d["feat"]
+    T, F, H, W = feat.shape
+    r, tr, C = cfg["r"], cfg["tr"], cfg["C"]
+    y = B.log_brightness(d["E"])
+    yref = B.log_brightness(d["E_ref"])
+    log(f"generated {W}x{H}x{T} with reference frames in {time.time() - t0:.1f}s")
+    taus, rmax = [5e-4, 2e-3, 5e-3, 1e-2], 0.05
+    pm = B.Params(r=r, tr=tr, C=C, multi_crossing=True)
+    ref = Simulator(yref, feat, pm, capacity=1 << 27).run("raw")
+    refd = Q.to_device(ref)
+    out = {"workload": f"every-crossing ESIM, DVS {W}x{H}x{T}, r={r}, tr={tr}, C={C}; reference = "
+                       f"every-crossing ESIM on the noise-free frames ({ref['count']} events)",
+           "taus": taus, "rmax": rmax}
+    stream = torch.cuda.current_stream()
+    for mode in ("raw", "exhaustive"):
+        for multi in (False, True):
+            p = B.Params(r=r, tr=tr, C=C, multi_crossing=multi)
+            sim = Simulator(y, feat, p, capacity=1 << 27)
+            run = _graph(lambda s=sim, m=mode: s.enqueue(m))
+            ms = _time_ms(run, max(1, args.steps))
+            ev = sim.events()
+            evd = Q.to_device(ev)
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            m = Q.metrics(evd, refd, W, H, T, taus, rmax)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            key = f"{mode}_{'every_crossing' if multi else 'one_per_frame'}"
+            out[key] = {"ms": round(ms, 3), "pixel_frames_per_s": round(T * H * W / (ms * 1e-3), 1),
+                        "events": ev["count"], "F": [round(v, 4) for v in m["F"]], "CD": m["CD"],
+                        "metrics_ms": round(e0.elapsed_time(e1), 3)}
+            log(f"{key}: {ms:.2f} ms, {ev['count']} events, F {out[key]['F']}, "
+                f"metrics {out[key]['metrics_ms']} ms")
+            del sim, run
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -516,7 +567,7 @@ def main():
     ap.add_argument("--schedule", type=str, default=None,
                     help="lanes_dense,lanes_list,blocks_per_cu (skips the autotuner)")
     ap.add_argument("--workload", choices=("dvs", "precision", "batch", "diff", "quality", "threshold",
-                                           "bandwidth"),
+                                           "bandwidth", "multicrossing"),
                     default="dvs",
                     help="dvs (default, the contract line) or one of the extension workloads")
     ap.add_argument("--copy-probe", action="store_true",
@@ -545,7 +596,7 @@ def main():
     if args.workload != "dvs":
         fn = {"precision": workload_precision, "batch": workload_batch, "diff": workload_diff,
               "quality": workload_quality, "threshold": workload_threshold,
-              "bandwidth": workload_bandwidth}
+              "bandwidth": workload_bandwidth, "multicrossing": workload_multicrossing}
         res = fn[args.workload](args, B, synth, Simulator)
         res = {"metric": f"{args.workload} workload", "n_gpus": 1, "dtype": "f64",
                "data": "synthetic", **res}

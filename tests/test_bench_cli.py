@@ -19,5 +19,5 @@ def test_workload_choices_are_listed():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--help"],
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 0
-    for w in ("dvs", "precision", "batch", "diff", "quality", "threshold", "bandwidth"):
+    for w in ("dvs", "precision", "batch", "diff", "quality", "threshold", "bandwidth", "multicrossing"):
         assert w in r.stdout
