@@ -1,7 +1,8 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark
 times (autotuned schedule), on outputs the oracle can compute one by one:
-sampled pixels' whole event histories, sampled regressions, sampled adjoint
-items, and a finite-difference check of the full differentiation loss."""
+sampled pixels' whole event histories (one event per pixel-frame and every
+crossing), sampled regressions, sampled adjoint items, and a finite-difference
+check of the full differentiation loss."""
 import numpy as np
 import pytest
 import torch
@@ -55,6 +56,64 @@ def test_dvs_events_on_sampled_pixels(dvs, mode):
     assert not fails, fails[:5]
     assert exc <= 2
     assert orc["count"] > 0
+
+
+def _sorted_by_pixel_frame(t, pix, *cols):
+    """Stable order by (t, pixel): keeps the crossings of a pixel-frame in
+    their emitted order."""
+    o = np.lexsort((pix, t))
+    return [c[o] for c in (t, pix) + cols]
+
+
+@pytest.mark.parametrize("mode", ["raw", "exhaustive"])
+def test_dvs_multicrossing_on_sampled_pixels(dvs, mode):
+    """Every-crossing events on the whole DVS clip, launched as the
+    every-crossing workload launches them (the step entry point), against the
+    oracle's every-crossing rule on sampled pixels' whole histories: frames,
+    polarities and counts exactly, times exactly (both sides take them in
+    FP64 and round once to FP32).  The compared values are the GPU's own FP32
+    inputs of the rule (y for raw; for exhaustive the per-frame alpha of the
+    separate calls, whose events must equal the step's bit for bit)."""
+    cfg = dvs["cfg"]
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"], multi_crossing=True)
+    T, F, H, W = dvs["fn"].shape
+    HW = H * W
+    say(f"DVS every-crossing {mode}")
+    sim = Simulator(dvs["y"], dvs["feat"], p, capacity=1 << 27)
+    gpu = sim.run(mode)
+    assert 0 < gpu["count"] < sim.ev.capacity
+    rng = np.random.default_rng(17)
+    gp = gpu["y"].astype(np.int64) * W + gpu["x"]
+    fired = np.unique(gp)
+    pix = np.unique(np.concatenate([rng.choice(HW, 64, replace=False),
+                                    rng.choice(fired, min(64, fired.size), replace=False)]))
+    if mode == "raw":
+        L = dvs["y"].reshape(T, HW)[:, torch.from_numpy(pix).cuda()].cpu().numpy()
+    else:
+        sep = Simulator(dvs["y"], dvs["feat"], p, capacity=1 << 27)
+        idx = torch.from_numpy(pix).cuda()
+        cols = []
+        sep.ev.count.zero_()
+        for t in range(T):
+            B.regress(sep.plan, t, None, None, HW, sep.alpha, None)
+            cols.append(sep.alpha[idx].clone())
+            B.events(sep.plan, t, B.EXHAUSTIVE, sep.ev, dl=sep.dl, alpha=sep.alpha, n_out=HW)
+        torch.cuda.synchronize()
+        L = torch.stack(cols).cpu().numpy()
+        ev_sep = sep.events()
+        for k in ("x", "y", "t", "p", "ts"):
+            assert np.array_equal(ev_sep[k], gpu[k]), k
+        del sep
+    orc = oracle.esim_multi_crossing(L, p.C, 1)       # W = 1: the column index is y
+    keep = np.isin(gp, pix)
+    g = _sorted_by_pixel_frame(gpu["t"][keep].astype(np.int64), gp[keep], gpu["p"][keep], gpu["ts"][keep])
+    o = _sorted_by_pixel_frame(orc["t"].astype(np.int64), pix[orc["y"]], orc["p"], orc["ts"])
+    say(f"DVS every-crossing {mode}: {pix.size} sampled pixels, {orc['count']} oracle events, "
+        f"{gpu['count']} events in all")
+    assert orc["count"] > pix.size
+    assert len(g[0]) == len(o[0])
+    for a, b in zip(g, o):
+        assert np.array_equal(a, b)
 
 
 @pytest.mark.parametrize("form", ["last", "new"])
