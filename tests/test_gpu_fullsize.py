@@ -1,8 +1,8 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark
 times (autotuned schedule), on outputs the oracle can compute one by one:
 sampled pixels' whole event histories (one event per pixel-frame and every
-crossing), sampled regressions, sampled adjoint items, and a finite-difference
-check of the full differentiation loss."""
+crossing), sampled regressions, the event-set comparison, sampled adjoint
+items, and a finite-difference check of the full differentiation loss."""
 import numpy as np
 import pytest
 import torch
@@ -178,6 +178,53 @@ def test_dvs_bandwidth_regression_on_sampled_pixels():
     assert flips <= 3
     ao = o["alpha_k"][rows, kg]
     assert np.max(np.abs(a.cpu().numpy()[pix] - ao) / np.maximum(1, np.abs(ao))) <= 1e-4
+
+
+def test_dvs_event_quality():
+    """The event-set comparison on the quality workload's full sets: the
+    thresholded conversion of the DVS clip against ESIM on its noise-free
+    frames, GPU precision, recall and Chamfer distance equal to the oracle's
+    (k-d tree per polarity) over all events; and raw ESIM's 28 M noisy events,
+    whose GPU nearest-neighbour distances are checked on a sample of queries."""
+    from oracle import metrics as OM
+    from paper_2303_02608_amd import quality as Q
+    cfg = synth.config_spec(1)
+    say("generate DVS 640x480x120 with reference frames")
+    d = synth.make_clip(cfg["spec"], device="cuda", reference=True)
+    feat = d["feat"]
+    T, F, H, W = feat.shape
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"])
+    ref = Simulator(B.log_brightness(d["E_ref"]), feat, p).run("raw")
+    y = B.log_brightness(d["E"])
+    taus, rmax = [5e-4, 2e-3, 5e-3, 1e-2], 0.05
+    keys = ("x", "y", "t", "p")
+    r = {k: ref[k] for k in keys}
+    gen = Simulator(y, feat, p).run("thresholded")
+    g = {k: gen[k] for k in keys}
+    m = Q.metrics(Q.to_device(g), Q.to_device(r), W, H, T, taus, rmax)
+    o = OM.metrics(g, r, W, H, T, taus, rmax)
+    say(f"DVS thresholded vs reference: {gen['count']} / {ref['count']} events, F {m['F']}")
+    assert m["P"] == pytest.approx(o["P"], rel=1e-12) and m["R"] == pytest.approx(o["R"], rel=1e-12)
+    assert m["CD"] == pytest.approx(o["CD"], rel=1e-12)
+    raw = Simulator(y, feat, p, capacity=1 << 26).run("raw")
+    assert raw["count"] < 1 << 26
+    q = {k: raw[k] for k in keys}
+    dist = B.nn_distances(Q.to_device(r), Q.to_device(q), W, H, T, rmax).cpu().numpy()
+    assert dist.size == raw["count"]
+    sel = np.random.default_rng(23).choice(raw["count"], 50000, replace=False)
+    od = OM.nn_distances(r, {k: v[sel] for k, v in q.items()}, W, H, T, rmax)
+    say(f"DVS raw: {raw['count']} queries, {sel.size} checked, {np.isfinite(od).mean():.3f} within rmax")
+    ds = dist[sel]
+    # a lattice offset of exactly rmax (32 columns, 24 rows or 6 frames at
+    # rmax = 0.05) is rounded to either side of rmax: the GPU scales integer
+    # offsets, the oracle subtracts scaled coordinates.  Such a distance is
+    # finite on one side and +inf on the other; elsewhere the two agree.
+    edge = (np.abs(ds - rmax) <= 1e-12 * rmax) | (np.abs(od - rmax) <= 1e-12 * rmax)
+    say(f"DVS raw: {int(edge.sum())} distances at rmax up to rounding")
+    assert np.array_equal(np.isinf(ds[~edge]), np.isinf(od[~edge]))
+    f = np.isfinite(od) & np.isfinite(ds)
+    assert np.allclose(ds[f], od[f], rtol=1e-12, atol=0)
+    assert np.all(np.isfinite(ds[edge]) | np.isfinite(od[edge]))
 
 
 def test_dvs_sampled_regressions(dvs):
