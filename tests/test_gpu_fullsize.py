@@ -1,8 +1,9 @@
 """Parity at the full workload sizes, in the launch configuration the benchmark
 times (autotuned schedule), on outputs the oracle can compute one by one:
 sampled pixels' whole event histories (one event per pixel-frame and every
-crossing), sampled regressions, the event-set comparison, sampled adjoint
-items, and a finite-difference check of the full differentiation loss."""
+crossing), sampled regressions, the event-set comparison, the 32-clip batch,
+sampled adjoint items, and a finite-difference check of the full
+differentiation loss."""
 import numpy as np
 import pytest
 import torch
@@ -247,6 +248,55 @@ def test_dvs_sampled_regressions(dvs):
         eb = np.abs(b.cpu().numpy()[:, pix].T - th[:, 1:]) / np.maximum(1, np.abs(th[:, 1:]))
         say(f"t={t}: alpha {ea.max():.2e} beta {eb.max():.2e}")
         assert ea.max() <= 1e-4 and eb.max() <= 1e-4
+
+
+def test_batch_workload_sampled():
+    """The 32-clip batch of the batching workload (frames scaled to 2e8
+    pixel-frames), launched as the benchmark launches it: each clip's batched
+    events equal its own conversion bit for bit, and sampled pixels of four
+    clips (the largest frame, the widest radius, the longest and the smallest)
+    match the oracle's whole histories."""
+    from paper_2303_02608_amd.simulator import BatchSimulator
+    specs = synth.batch_specs(32, seed=5000, max_pixel_frames=2e8)
+    area = [c["spec"].W * c["spec"].H for c in specs]
+    pick = sorted({int(np.argmax(area)), int(np.argmax([c["r"] for c in specs])),
+                   int(np.argmax([c["spec"].T for c in specs])), int(np.argmin(area))})
+    say(f"generate the 32-clip batch; oracle clips {pick}")
+    ys, feats, params, host = [], [], [], {}
+    for i, c in enumerate(specs):
+        d = synth.make_clip(c["spec"], device="cuda")
+        ys.append(B.log_brightness(d["E"]))
+        feats.append(d["feat"])
+        params.append(B.Params(r=c["r"], tr=c["tr"], C=c["C"]))
+        if i in pick:
+            host[i] = (d["E"].cpu().numpy(), d["feat"].cpu().numpy())
+        del d
+    bs = BatchSimulator(ys, feats, params)
+    got = bs.run()
+    say(f"batch: {got['count']} events")
+    assert 0 < got["count"] < bs.ev.capacity
+    for c in range(len(specs)):
+        m = got["clip"] == c
+        single = Simulator(ys[c], feats[c], params[c]).run("thresholded")
+        for k in ("x", "y", "t", "p"):
+            assert np.array_equal(got[k][m], single[k]), (c, k)
+    rng = np.random.default_rng(29)
+    for c in pick:
+        E, feat = host[c]
+        T, F, H, W = feat.shape
+        p = params[c]
+        m = got["clip"] == c
+        g = {k: got[k][m] for k in ("x", "y", "t", "p")}
+        fired = np.unique(g["y"].astype(np.int64) * W + g["x"])
+        pix = np.unique(np.concatenate([rng.choice(H * W, 24, replace=False),
+                                        rng.choice(fired, min(24, fired.size), replace=False)]))
+        orc = oracle.run(oracle.Clip(oracle.log_brightness(E), feat), oracle.Params(p.r, p.tr, p.C),
+                         oracle.THRESHOLDED, pixels=pix, want_dl=True)
+        n, exc, fails = compare_events(g, orc, W, p.C, 1e-4, pixels=pix)
+        say(f"clip {c} ({W}x{H}x{T}, r={p.r}): {n} sampled pixels, {orc['count']} oracle events, "
+            f"excused {exc}")
+        assert not fails, (c, fails[:5])
+        assert exc <= 2
 
 
 @pytest.fixture(scope="module")
