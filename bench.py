@@ -549,6 +549,26 @@ def workload_multicrossing(args, B, synth, Simulator):
     return out
 
 
+def cpu_baseline(E, feat, r, tr, C, n_pixels):
+    """The FP64 oracle, as it stands, on the host cores: the thresholded path
+    over the whole clip for a random sample of pixels (their complete
+    histories), scaled to pixel-frames/s.  The only use of the oracle here."""
+    import oracle
+    T, F, H, W = feat.shape
+    nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
+    rng = np.random.default_rng(1234)
+    pix = np.sort(rng.choice(H * W, size=min(n_pixels, H * W), replace=False))
+    oc = oracle.Clip(oracle.log_brightness(E.cpu().numpy()), feat.cpu().numpy())
+    c0 = time.perf_counter()
+    out = oracle.run(oc, oracle.Params(r, tr, C), oracle.THRESHOLDED, pixels=pix, nthreads=nthreads)
+    secs = time.perf_counter() - c0
+    log(f"oracle: {secs:.1f}s for {pix.size} px x {T} frames ({nthreads} threads)")
+    return {"value": round(pix.size * T / secs, 1), "unit": "pixel-frames/s", "cores": nthreads,
+            "kind": "oracle",
+            "sample": f"{pix.size} random pixels x {T} frames of the same clip, thresholded "
+                      f"path, FP64, {secs:.1f}s; events/s {out['count'] / secs:.1f}"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--gpus", type=int, default=1)
@@ -766,24 +786,7 @@ def main():
         exh["regress_frac"] = round(exh["regress_tflops"] / PEAK_ALU_TFLOPS, 4)
 
     # ---- CPU baseline: the FP64 oracle on a random pixel sample -----------
-    cpu = None
-    if not args.no_cpu_baseline:
-        import oracle
-        nthreads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count()
-        rng = np.random.default_rng(1234)
-        pix = np.sort(rng.choice(H * W, size=min(args.cpu_pixels, H * W), replace=False))
-        En = E.cpu().numpy()
-        fn = feat.cpu().numpy()
-        oc = oracle.Clip(oracle.log_brightness(En), fn)
-        c0 = time.perf_counter()
-        out = oracle.run(oc, oracle.Params(r, tr, C), oracle.THRESHOLDED, pixels=pix,
-                         nthreads=nthreads)
-        secs = time.perf_counter() - c0
-        cpu = {"value": round(pix.size * T / secs, 1), "unit": "pixel-frames/s", "cores": nthreads,
-               "kind": "oracle",
-               "sample": f"{pix.size} random pixels x {T} frames of the same clip, thresholded "
-                         f"path, FP64, {secs:.1f}s; events/s {out['count'] / secs:.1f}"}
-        log(f"oracle: {secs:.1f}s for {pix.size} px x {T} frames ({nthreads} threads)")
+    cpu = None if args.no_cpu_baseline else cpu_baseline(E, feat, r, tr, C, args.cpu_pixels)
 
     res = {
         "metric": METRIC,

@@ -95,3 +95,42 @@ def test_bad_shapes_and_params_are_rejected(lib):
                                B.Params(r=5, tr=0, C=0.2, threshold=B.THRESHOLD_NEW_WINDOW).struct(F))
     clips = (B.esim_clip * 2)(clip, clip)
     assert lib.esim_plan_create(clips, pars, None, 2, ctypes.byref(out)) == B.E_UNSUPPORTED
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No CPU fallback: without the built library every entry point raises."""
+    monkeypatch.setattr(B, "_lib", None)
+    with pytest.raises(ImportError, match="not built"):
+        B.load(str(tmp_path / "libesim.so"))
+    monkeypatch.setattr(B, "LIB_PATH", str(tmp_path / "libesim.so"))
+    monkeypatch.setattr(B.load, "__defaults__", (str(tmp_path / "libesim.so"),))
+    with pytest.raises(ImportError, match="not built"):
+        B.log_brightness(__import__("torch").zeros(4))
+
+
+def test_product_code_never_reaches_the_oracle():
+    """The package imports nothing from the oracle, and the benchmark only in
+    its CPU-baseline leg."""
+    import ast
+    pkg = os.path.join(ROOT, "paper_2303_02608_amd")
+    for name in sorted(os.listdir(pkg)):
+        if not name.endswith(".py"):
+            continue
+        tree = ast.parse(open(os.path.join(pkg, name)).read())
+        for node in ast.walk(tree):
+            mods = ([a.name for a in node.names] if isinstance(node, ast.Import)
+                    else [node.module or ""] if isinstance(node, ast.ImportFrom) else [])
+            assert not any(m == "oracle" or m.startswith("oracle.") for m in mods), name
+    tree = ast.parse(open(os.path.join(ROOT, "bench.py")).read())
+    users = set()
+    for fn in ast.walk(tree):
+        if isinstance(fn, ast.FunctionDef):
+            for node in ast.walk(fn):
+                if isinstance(node, (ast.Import, ast.ImportFrom)):
+                    mods = ([a.name for a in node.names] if isinstance(node, ast.Import) else [node.module or ""])
+                    if any(m == "oracle" or m.startswith("oracle.") for m in mods):
+                        users.add(fn.name)
+    top = [n for n in tree.body if isinstance(n, (ast.Import, ast.ImportFrom))]
+    assert not any((isinstance(n, ast.Import) and any(a.name.startswith("oracle") for a in n.names)) or
+                   (isinstance(n, ast.ImportFrom) and (n.module or "").startswith("oracle")) for n in top)
+    assert users and all("cpu" in u for u in users), users

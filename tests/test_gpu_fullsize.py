@@ -360,7 +360,7 @@ def test_diff_loss_gradient_full_size(diff_clip):
             vals.append(float(_loss(a2, prev, HW)))
         fd = (vals[0] - vals[1]) / (2 * h)
         say(f"dL/db_{j}: adjoint {g[j]:.6e} central FD {fd:.6e}")
-        assert g[j] == pytest.approx(fd, rel=2e-3, abs=1e-6 * abs(float(loss)))
+        assert g[j] == pytest.approx(fd, rel=2e-3, abs=1e-6 * abs(loss.detach().item()))
 
 
 def test_diff_sampled_adjoint_items(diff_clip):
