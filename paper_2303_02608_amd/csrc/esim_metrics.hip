@@ -8,13 +8,15 @@
 //   bitmap_set_kernel    one bit per source event in the bitmap of its
 //                        polarity: [2][T][H][ceil(W / 32)] words (atomicOr:
 //                        the result does not depend on the order)
-//   nn_kernel            per query event: for every frame and row of the box
-//                        |dt| <= rt, |dy| <= ry, the nearest set bit of the
-//                        row within |dx| <= rx of the query column (count
-//                        leading/trailing zeros over the row's words); the
-//                        smallest scaled distance (FP64) wins.  With rx, ry,
-//                        rt the lattice extents of the radius rmax, this is the
-//                        exact nearest neighbour within rmax.
+//   nn_kernel            per query event: for the frames and rows of the box
+//                        |dt| <= rt, |dy| <= ry, visited centre-out, the
+//                        nearest set bit of the row within |dx| <= rx of the
+//                        query column (count leading/trailing zeros over the
+//                        row's words); the smallest scaled distance (FP64)
+//                        wins, and rows whose (dt, dy) offset alone cannot beat
+//                        it are not visited.  With rx, ry, rt the lattice
+//                        extents of the radius rmax, this is the exact nearest
+//                        neighbour within rmax.
 #include <cmath>
 #include <cstdint>
 
@@ -89,16 +91,22 @@ nn_kernel(const uint32_t* __restrict__ bm, const int32_t* __restrict__ qx, const
     if (xi >= 0 && xi < W && yi >= 0 && yi < H && ti >= 0 && ti < T && (pi == 1 || pi == -1)) {
       const int pl = pi > 0 ? 0 : 1;
       const int lo = max(0, xi - rx), hi = min(W - 1, xi + rx);
-      for (int dt = -rt; dt <= rt; ++dt) {
+      // frames and rows centre-out (0, -1, +1, -2, +2, ...): |dt| and |dy| never
+      // decrease, so once a row's offset alone reaches the best distance every
+      // later row of the frame (and, at dy = 0, every later frame) does too
+      for (int kt = 0; kt <= 2 * rt; ++kt) {
+        const int dt = (kt & 1) ? -((kt + 1) >> 1) : (kt >> 1);
+        const double et = dt * st;
+        if (et * et >= best) break;
         const int tc = ti + dt;
         if (tc < 0 || tc >= T) continue;
-        const double et = dt * st;
-        for (int dy = -ry; dy <= ry; ++dy) {
-          const int yc = yi + dy;
-          if (yc < 0 || yc >= H) continue;
+        for (int ky = 0; ky <= 2 * ry; ++ky) {
+          const int dy = (ky & 1) ? -((ky + 1) >> 1) : (ky >> 1);
           const double ey = dy * sy;
           const double base = fma(et, et, ey * ey);
-          if (base >= best) continue;
+          if (base >= best) break;
+          const int yc = yi + dy;
+          if (yc < 0 || yc >= H) continue;
           const uint32_t* row = bm + ((static_cast<int64_t>(pl) * T + tc) * H + yc) * wpr;
           const int dx = nearest_bit(row, xi, lo, hi);
           if (dx >= 0) {
