@@ -1,6 +1,7 @@
 // Threshold, compaction, event emission and state updates (HBM-bound).
 //
-//   log_kernel         Sec. 1.1: y = log(E + eps).
+//   log_kernel         Sec. 1.1: y = log(E + eps) (log4_kernel: 16-byte
+//                      accesses when both arrays are 16-byte aligned).
 //   flag_kernel        per pixel of a 256-pixel block:
 //                        threshold  - Prop. 1 / eqs. 8-9: dL = beta_ref^T (f_t -
 //                                     x_ref) over the F buffer channels (the
@@ -35,6 +36,25 @@ __global__ void __launch_bounds__(256) log_kernel(const float* __restrict__ E, f
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
   for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n; i += stride)
     y[i] = logf(E[i] + eps);
+}
+
+// The same with 16-byte accesses (both pointers 16-byte aligned): four values
+// per lane and iteration; the n % 4 last values by the first lanes.
+__global__ void __launch_bounds__(256) log4_kernel(const float4* __restrict__ E, float4* __restrict__ y,
+                                                   int64_t n, float eps) {
+  const int64_t n4 = n >> 2;
+  const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+  const int64_t id = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+  for (int64_t i = id; i < n4; i += stride) {
+    const float4 e = E[i];
+    y[i] = make_float4(logf(e.x + eps), logf(e.y + eps), logf(e.z + eps), logf(e.w + eps));
+  }
+  const int64_t tail = n - (n4 << 2);
+  if (id < tail) {
+    const float* Es = reinterpret_cast<const float*>(E);
+    float* ys = reinterpret_cast<float*>(y);
+    ys[(n4 << 2) + id] = logf(Es[(n4 << 2) + id] + eps);
+  }
 }
 
 // Levels L_ref + k p C passed by a change d (every-crossing rule): floor(|d| / C),
@@ -348,10 +368,16 @@ init_kernel(const ClipDev* __restrict__ clips, int nclips, int t, const float* _
 }  // namespace
 
 hipError_t launch_log(const float* E, float* y, int64_t n, float eps, hipStream_t s) {
-  int64_t blocks = (n + 255) / 256;
+  const bool vec = (reinterpret_cast<uintptr_t>(E) % 16 == 0) && (reinterpret_cast<uintptr_t>(y) % 16 == 0);
+  const int64_t per = vec ? 4 : 1;
+  int64_t blocks = (n / per + 255) / 256;
   if (blocks > 65536) blocks = 65536;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(log_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, E, y, n, eps);
+  if (vec)
+    hipLaunchKernelGGL(log4_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s,
+                       reinterpret_cast<const float4*>(E), reinterpret_cast<float4*>(y), n, eps);
+  else
+    hipLaunchKernelGGL(log_kernel, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, E, y, n, eps);
   return hipGetLastError();
 }
 

@@ -78,6 +78,14 @@ def test_log_brightness_matches_oracle():
     y = B.log_brightness(torch.from_numpy(E).cuda()).cpu().numpy()
     ref = oracle.log_brightness(E)
     assert np.max(np.abs(y - ref) / np.maximum(1.0, np.abs(ref))) <= 2.5e-7
+    # input 4 bytes off a 16-byte boundary: the one-value-per-lane kernel, the
+    # same values bit for bit
+    buf = torch.empty(E.size + 1, device="cuda")
+    Eoff = buf[1:]
+    Eoff.copy_(torch.from_numpy(E))
+    assert Eoff.data_ptr() % 16 != 0
+    y2 = B.log_brightness(Eoff).cpu().numpy()
+    assert np.array_equal(y2.view(np.uint32), y.view(np.uint32))
 
 
 @pytest.mark.parametrize("t", [0, 7, 15])
