@@ -136,9 +136,18 @@ __device__ __forceinline__ void bandwidth_item(const BandwidthArgs& a, const Cli
   }
 }
 
+// Up to 8 features the window loop's accumulators fit half the register file:
+// two waves per SIMD, as for the regression (a wave's memory and scalar work
+// then issues beside the other wave's FMAs).
+template <int F>
+constexpr int bandwidth_waves_per_simd() {
+  return F <= 8 ? 2 : 1;
+}
+
 // Dense: one lane per pixel of frame t.
 template <int F, bool F16>
-__global__ void __launch_bounds__(256) bandwidth_dense_kernel(BandwidthArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bandwidth_waves_per_simd<F>())))
+bandwidth_dense_kernel(BandwidthArgs a) {
   const ClipDev& C = *a.clip;
   const int64_t n = C.HW;
   const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
@@ -155,7 +164,8 @@ __global__ void __launch_bounds__(256) bandwidth_dense_kernel(BandwidthArgs a) {
 // lane owns one column.
 constexpr int kListLanes = 16;
 template <int F, bool F16, bool ONE>
-__global__ void __launch_bounds__(256) bandwidth_list_kernel(BandwidthArgs a) {
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(bandwidth_waves_per_simd<F>())))
+bandwidth_list_kernel(BandwidthArgs a) {
   const ClipDev& C = *a.clip;
   const int64_t n = max(static_cast<int64_t>(0), min(static_cast<int64_t>(a.count[0]), a.n_out));
   constexpr int ipb = 256 / kListLanes;
