@@ -340,8 +340,9 @@ int esim_log_variance(const float* E, const float* var, int32_t spp, float* vy, 
  * worklist NULL, every pixel (index p, n_out >= H*W).  Outputs: alpha[i];
  * beta[d * n_out + i] over D (nullable); hsel[i] the chosen h (nullable);
  * sure[i] its SURE (nullable).  vy: [T][H][W], the variance of y
- * (esim_log_variance).  Single-clip plans, FP64 Gram; one lane per item, K
- * window passes per item.
+ * (esim_log_variance).  Single-clip plans, FP64 Gram; K window passes per
+ * item (one lane per pixel for every pixel of the frame, 16 lanes per item for
+ * work lists).
  * Errors: E_INVAL (K outside 1..8, h <= 0, null pointers, n_out),
  * E_UNSUPPORTED (several clips). */
 int esim_wlr_regress_bandwidth(esim_plan plan, int32_t t, const int64_t* worklist, const int32_t* count,
