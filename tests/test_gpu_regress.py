@@ -86,6 +86,12 @@ def test_log_brightness_matches_oracle():
     assert Eoff.data_ptr() % 16 != 0
     y2 = B.log_brightness(Eoff).cpu().numpy()
     assert np.array_equal(y2.view(np.uint32), y.view(np.uint32))
+    # lengths below and around one 16-byte vector (tail lanes only, or a few
+    # vectors and a tail)
+    for n in (1, 2, 3, 4, 5, 7):
+        yn = B.log_brightness(torch.from_numpy(E[:n].copy()).cuda()).cpu().numpy()
+        assert np.array_equal(yn.view(np.uint32), y[:n].view(np.uint32)), n
+    assert B.log_brightness(torch.empty(0, device="cuda")).numel() == 0
 
 
 @pytest.mark.parametrize("t", [0, 7, 15])
