@@ -127,8 +127,7 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
             pred = fma(th[3 + f], v[f], pred);
           }
           const double res = yd - pred;
-          // only in-image samples have a slot the gather reads; the padding
-          // row of an odd row count lies past the window and is skipped
+          // only in-image samples have a slot the gather reads
           if (ok) ci[((dt + tr) * span + (dy + r)) * span + (dx + r)] = static_cast<float>(ga * w * iW * s);
           const double k = ga * (s * res - vLt) * iW * w;
           gb[0] = fma(k, cur_vx * cur_vx, gb[0]);

@@ -66,16 +66,17 @@ __device__ __forceinline__ void make_geom(ItemGeom<F, F16, Real>& g, const ClipD
 
 // Runs the window of one item in lane j of its L-lane group.
 //   pass_begin(vx)                      before each column pass
-//   sample(w, yd, v[F], vy, dx, dt, dy, ok) for every sample; ok is false
-//                                       (and w = 0) outside the image, for
-//                                       idle columns and for the weight-0
-//                                       padding rows past the last row, whose
-//                                       (dt, dy) lie past the window
+//   sample(w, yd, v[F], vy, dx, dt, dy, ok) for every row of the window in
+//                                       the lane's column; ok is false (and
+//                                       w = 0) outside the image and for idle
+//                                       columns
 //   pass_end(vx)                        after each column pass
 //
 // The rows of a column form a three-stage software pipeline: the loads of row
 // k+2 are in flight while the weight of row k+1 is computed and row k is
 // accumulated, so the exponential's latency overlaps independent Gram work.
+// The loop takes two rows per iteration; an odd last row is accumulated after
+// it on its own.
 // Row offsets advance by uniform (SGPR) amounts; only the validity test and
 // the select are per lane.
 template <int F, int L, bool F16, class Real, class PassBegin, class Sample, class PassEnd>
@@ -158,8 +159,9 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
     Wt wA, wB;
     weigh(yA, fA, okA, wA);
     okA = load_row(yA, fA) & (2 < nrows);
+    int q = 0;
 #pragma unroll 1
-    for (int q = 0; q < nrows; q += 2) {
+    for (; q + 1 < nrows; q += 2) {
       // wA = row q (weighed), raw B = row q+1, raw A = row q+2
       weigh(yB, fB, okB, wB);
       okB = load_row(yB, fB) & (q + 3 < nrows);
@@ -168,6 +170,7 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
       okA = load_row(yA, fA) & (q + 4 < nrows);
       use(wB);
     }
+    if (q < nrows) use(wA);       // odd row count: the last row alone
     pass_end(vx);
   }
 }
