@@ -563,10 +563,18 @@ def cpu_baseline(E, feat, r, tr, C, n_pixels):
     out = oracle.run(oc, oracle.Params(r, tr, C), oracle.THRESHOLDED, pixels=pix, nthreads=nthreads)
     secs = time.perf_counter() - c0
     log(f"oracle: {secs:.1f}s for {pix.size} px x {T} frames ({nthreads} threads)")
+    # WLR+ESIM beside it: every frame of a smaller random pixel sample
+    pe = np.sort(rng.choice(H * W, size=min(8000, H * W), replace=False))
+    c0 = time.perf_counter()
+    oe = oracle.run(oc, oracle.Params(r, tr, C), oracle.EXHAUSTIVE, pixels=pe, nthreads=nthreads)
+    se = time.perf_counter() - c0
+    log(f"oracle, exhaustive: {se:.1f}s for {pe.size} px x {T} frames")
     return {"value": round(pix.size * T / secs, 1), "unit": "pixel-frames/s", "cores": nthreads,
             "kind": "oracle",
             "sample": f"{pix.size} random pixels x {T} frames of the same clip, thresholded "
-                      f"path, FP64, {secs:.1f}s; events/s {out['count'] / secs:.1f}"}
+                      f"path, FP64, {secs:.1f}s; events/s {out['count'] / secs:.1f}",
+            "exhaustive": {"value": round(pe.size * T / se, 1), "unit": "pixel-frames/s",
+                           "sample": f"{pe.size} random pixels x {T} frames, WLR+ESIM, FP64, {se:.1f}s"}}
 
 
 def main():
