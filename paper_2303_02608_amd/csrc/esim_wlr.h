@@ -13,6 +13,8 @@
 // (or past the last row) read the valid centre pixel and get weight 0.
 #pragma once
 
+#include <type_traits>
+
 #include "esim_internal.h"
 
 namespace esim {
@@ -75,8 +77,7 @@ __device__ __forceinline__ void make_geom(ItemGeom<F, F16, Real>& g, const ClipD
 // The rows of a column form a three-stage software pipeline: the loads of row
 // k+2 are in flight while the weight of row k+1 is computed and row k is
 // accumulated, so the exponential's latency overlaps independent Gram work.
-// The loop takes two rows per iteration; an odd last row is accumulated after
-// it on its own.
+// The loop takes two rows per iteration (see the loop for an odd row count).
 // Row offsets advance by uniform (SGPR) amounts; only the validity test and
 // the select are per lane.
 template <int F, int L, bool F16, class Real, class PassBegin, class Sample, class PassEnd>
@@ -159,9 +160,14 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
     Wt wA, wB;
     weigh(yA, fA, okA, wA);
     okA = load_row(yA, fA) & (2 < nrows);
+    // FP64: pairs of rows, then an odd last row alone.  FP32 (the compensated
+    // variant, whose per-sample body is larger): pairs only, an odd count
+    // ending on a weight-0 padding row, which measured faster there.
+    constexpr bool kPeel = std::is_same<Real, double>::value;
+    const int qend = kPeel ? nrows - 1 : nrows;
     int q = 0;
 #pragma unroll 1
-    for (; q + 1 < nrows; q += 2) {
+    for (; q < qend; q += 2) {
       // wA = row q (weighed), raw B = row q+1, raw A = row q+2
       weigh(yB, fB, okB, wB);
       okB = load_row(yB, fB) & (q + 3 < nrows);
@@ -170,7 +176,9 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
       okA = load_row(yA, fA) & (q + 4 < nrows);
       use(wB);
     }
-    if (q < nrows) use(wA);       // odd row count: the last row alone
+    if constexpr (kPeel) {
+      if (q < nrows) use(wA);     // odd row count: the last row alone
+    }
     pass_end(vx);
   }
 }
