@@ -311,3 +311,52 @@ def test_thresholded_feature_counts_and_f16(F, feat_dtype, r, tr):
     say(f"gpu {gpu['count']} oracle {orc['count']} excused {excused}")
     assert gpu["count"] > 0
     assert not fails and excused <= max(2, n // 1000), fails[:5]
+
+
+@pytest.mark.parametrize("ridge", [0.0, 1e-6])
+def test_flat_features_and_nan_inputs_match_oracle(ridge):
+    """Degenerate values (the failure policy): a block whose features are the
+    same at every pixel and frame (its windows' feature columns are exactly
+    zero: with ridge 0 the Gram is singular and the regression gives NaN, with
+    a ridge beta_f is 0), a NaN brightness sample and a NaN feature sample
+    (NaN reaches every regression whose window holds them).  The dense
+    regression's NaN pattern and finite values, and every mode's events, equal
+    the oracle's: a NaN model or change never fires."""
+    W, H, T, F = 40, 32, 6, 3
+    d = synth.random_features_clip(W, H, T, F, seed=77)
+    E, feat = d["E"].numpy().copy(), d["feat"].numpy().copy()
+    feat[:, :, 4:16, 4:16] = 0.5
+    E[2, 20, 30] = np.nan
+    feat[3, 1, 25, 10] = np.nan
+    p = B.Params(r=2, tr=1, C=0.05, ridge=ridge)
+    say(f"flat block and NaN inputs, ridge {ridge}")
+    y, fd = to_dev(E, feat)
+    plan = B.Plan([y], [fd], [p])
+    HW = H * W
+    a = torch.empty(HW, device="cuda")
+    b = torch.empty((F + 2, HW), device="cuda")
+    oc = oracle_clip(E, feat)
+    op = oracle.Params(p.r, p.tr, p.C, p.h, p.b, p.ridge)
+    for t in (0, 2, 3):
+        B.regress(plan, t, None, None, HW, a, b)
+        torch.cuda.synchronize()
+        ga = a.cpu().numpy()
+        th = oracle.regress_items(oc, op, t * HW + np.arange(HW))["theta"]
+        nan_g, nan_o = np.isnan(ga), np.isnan(th[:, 0])
+        assert np.array_equal(nan_g, nan_o), (t, np.sum(nan_g), np.sum(nan_o))
+        # NaN comes from the singular flat windows (ridge 0) or from the NaN
+        # samples (in the windows of frames 1..4)
+        assert nan_g.any() == (ridge == 0.0 or t in (2, 3))
+        ok = ~nan_o
+        assert np.max(np.abs(ga[ok] - th[ok, 0]) / np.maximum(1, np.abs(th[ok, 0]))) <= 1e-4
+        if ridge > 0:
+            inner = np.zeros((H, W), bool)
+            inner[6:14, 6:14] = True              # windows entirely inside the block
+            inner = inner.reshape(-1) & ok
+            assert np.all(b.cpu().numpy()[2:, inner] == 0.0)
+    for mode in ("thresholded", "exhaustive", "raw"):
+        gpu, _ = run_gpu(E, feat, p, mode)
+        orc = _oracle_run(E, feat, p, mode)
+        n, excused, fails = compare_events(gpu, orc, W, p.C, BAND)
+        say(f"ridge {ridge} {mode}: {gpu['count']} events, oracle {orc['count']}, excused {excused}")
+        assert not fails and excused <= 1, (mode, fails[:5])
