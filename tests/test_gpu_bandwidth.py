@@ -200,3 +200,51 @@ def test_eight_candidates(clip):
     hs_sorted = np.asarray(hs)[order]
     o_sorted = dict(o, sure=o["sure"][:, order], alpha_k=o["alpha_k"][:, order])
     _compare(g, o_sorted, pix, hs=hs_sorted)
+
+
+def test_bandwidth_conversion_graph_replays(clip):
+    """The thresholded conversion with the bandwidth chosen per regression (as
+    the bandwidth workload captures it): graph replays, with eager work and
+    synchronisation between them, reproduce the eager run's events bit for bit."""
+    from paper_2303_02608_amd.simulator import Simulator
+    cfg = clip["cfg"]
+    p = B.Params(r=cfg["r"], tr=1, C=cfg["C"])
+    say("bandwidth conversion: graph replays")
+    E = torch.from_numpy(clip["E"]).cuda()
+    feat = torch.from_numpy(clip["feat"]).cuda()
+    y = B.log_brightness(E)
+    vy = B.log_variance(E, torch.from_numpy(clip["var"]).cuda(), clip["spp"])
+    T, F, H, W = feat.shape
+    sim = Simulator(y, feat, p)
+    plan, n = sim.plan, H * W
+
+    def convert():
+        sim.ev.count.zero_()
+        B.regress_bandwidth(plan, 0, None, None, n, vy, HS, sim.alpha, sim.beta)
+        B.events(plan, 0, B.INIT, None, alpha=sim.alpha, beta=sim.beta, n_out=n)
+        for t in range(1, T):
+            B.threshold(plan, t, sim.dl, sim.worklist, sim.count)
+            B.regress_bandwidth(plan, t, sim.worklist, sim.count, n, vy, HS, sim.alpha, sim.beta)
+            B.events(plan, t, B.THRESHOLDED, sim.ev, worklist=sim.worklist, count=sim.count, dl=sim.dl,
+                     alpha=sim.alpha, beta=sim.beta, n_out=n)
+
+    convert()
+    torch.cuda.synchronize()
+    eager = sim.events()
+    assert eager["count"] > 0
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        convert()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        convert()
+    for _ in range(3):
+        g.replay()
+        torch.cuda.synchronize()
+        got = sim.events()
+        for k in ("x", "y", "t", "p"):
+            assert np.array_equal(got[k], eager[k]), k
+        _ = (y * 2).sum().item()
