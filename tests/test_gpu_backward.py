@@ -89,3 +89,46 @@ def test_backward_accumulates_and_is_deterministic(small_clip):
     torch.cuda.synchronize()
     assert torch.allclose(outs[0][0], 2 * gy1, rtol=1e-6, atol=1e-9)
     assert torch.allclose(outs[0][1], 2 * gb1, rtol=1e-12, atol=0)
+
+
+def test_backward_graph_replays(small_clip):
+    """esim_wlr_backward captured in a graph (after zeroing its accumulated
+    outputs with fill kernels): replays, with eager work and synchronisation
+    between them, give the eager gradients bit for bit."""
+    E, feat = small_clip["E"][:5], small_clip["feat"][:5]
+    T, F, H, W = feat.shape
+    say("backward graph replays")
+    y, fd = to_dev(E, feat)
+    plan = B.Plan([y], [fd], [B.Params(4, 1, 0.2)])
+    rng = np.random.default_rng(3)
+    items_np = np.unique(rng.integers(0, T * H * W, size=500))
+    items = torch.from_numpy(((items_np // (H * W)) << 44) | (items_np % (H * W))).cuda()
+    ga = torch.from_numpy(rng.standard_normal(items_np.size)).float().cuda()
+    scratch = torch.empty(B.backward_scratch_bytes(plan, items.numel()), dtype=torch.uint8, device="cuda")
+    gy = torch.zeros_like(y)
+    gb = torch.zeros(F + 2, dtype=torch.float64, device="cuda")
+
+    def run():
+        gy.zero_()
+        gb.zero_()
+        B.backward(plan, items, ga, gy, gb, scratch)
+
+    run()
+    torch.cuda.synchronize()
+    ref_y, ref_b = gy.clone(), gb.clone()
+    assert torch.count_nonzero(ref_y) > 0
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        run()
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        run()
+    for _ in range(3):
+        gy.fill_(1.0)
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(gy, ref_y) and torch.equal(gb, ref_b)
+        _ = (y * 2).sum().item()
