@@ -65,3 +65,37 @@ def test_metrics_on_the_small_workload(small_clip):
         say(f"{mode}: F {m['F']} CD {m['CD']:.3e}")
         assert m["P"] == pytest.approx(o["P"], rel=1e-12) and m["R"] == pytest.approx(o["R"], rel=1e-12)
         assert m["CD"] == pytest.approx(o["CD"], rel=1e-12)
+
+
+def test_nn_distances_in_a_graph():
+    """esim_nn_distances captured in a graph (the bitmap clear is a fill kernel):
+    replays after the source events change in place give the eager distances
+    of the new events, bit for bit."""
+    W, H, T, rmax = 96, 64, 12, 0.08
+    say("nn distances in a graph")
+    src_np = _random_set(4000, W, H, T, 11)
+    qry_np = _random_set(3000, W, H, T, 12)
+    src, qry = Q.to_device(src_np), Q.to_device(qry_np)
+    scratch = torch.empty(int(B.load().esim_nn_scratch_bytes(W, H, T)), dtype=torch.uint8, device="cuda")
+    B.nn_distances(src, qry, W, H, T, rmax, scratch=scratch)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        B.nn_distances(src, qry, W, H, T, rmax, scratch=scratch)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        out = B.nn_distances(src, qry, W, H, T, rmax, scratch=scratch)
+    rng = np.random.default_rng(5)
+    for k in range(3):
+        if k:
+            # move the source events: a stale bitmap would keep the old ones
+            src["x"].copy_(torch.from_numpy(rng.integers(0, W, src_np["x"].size).astype(np.int32)).cuda())
+        g.replay()
+        torch.cuda.synchronize()
+        ref = B.nn_distances(src, qry, W, H, T, rmax, scratch=torch.empty_like(scratch))
+        torch.cuda.synchronize()
+        assert torch.equal(out, ref), k
+        _ = (ref * 2).sum().item()
