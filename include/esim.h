@@ -123,6 +123,9 @@ typedef struct {
                               2^20 per pixel-frame).  Needs the state's `last`.
                               Ignored by the thresholded mode.                  */
   int32_t threshold;       /* esim_threshold; the same for every clip of a plan  */
+  double dt;               /* time between frames, > 0 and finite (Sec. 3: the
+                              frames are rendered at fixed times; the DVS
+                              workload uses 1 ms): event times are t * dt     */
 } esim_params;
 
 /* Per-pixel reference state (Sec. 2.2: one regression model per pixel, kept
@@ -153,9 +156,9 @@ typedef struct {
  * events of one pixel-frame in time order); an event whose index reaches
  * `capacity` is dropped but still counted, so a caller detects overflow by
  * *count > capacity after synchronising.  `clip` and `ts` may be NULL.
- * Timestamps are frame indices (time = t * dt); `ts` receives the event's
- * time in frame units: t itself, or with multi_crossing the interpolated
- * crossing time in (t - 1, t]. */
+ * `t` receives the frame index; `ts` the event's time in the unit of the
+ * clip's dt: t * dt, or with multi_crossing the interpolated crossing time
+ * in ((t - 1) * dt, t * dt]. */
 typedef struct {
   int32_t* x;
   int32_t* y;
@@ -236,7 +239,8 @@ int esim_wlr_threshold(esim_plan plan, int32_t t, float* dl, int64_t* worklist,
  *   - every pixel of every clip active at t (worklist == NULL; the results of
  *     pixel p of clip c go to index pixel_offset(c) + p).
  * If t >= 0 every item is regressed at frame t; if t < 0 each item carries its
- * frame in bits [44,63) (then every clip's feature array must stay below 4 GiB).
+ * frame in bits [44,63) (then every clip's feature and brightness arrays must
+ * stay below 4 GiB).
  * Outputs (n_out = stride of beta, >= the largest index written):
  *   alpha[i]          = fitted value at the centre (eq. 3's f(x^c)),
  *   beta[d * n_out + i] (nullable) = gradient over the D = F + 2 features,
@@ -251,7 +255,7 @@ int esim_wlr_threshold(esim_plan plan, int32_t t, float* dl, int64_t* worklist,
  *                       decides the FP64 re-solve (re-solved iff it exceeds
  *                       kappa_fp64 or is not finite).
  * Errors: E_INVAL (null outputs, n_out too small for dense mode),
- * E_UNSUPPORTED (t < 0 with a clip of 4 GiB or more of features). */
+ * E_UNSUPPORTED (t < 0 with a clip of 4 GiB or more of features or brightness). */
 int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const int32_t* count,
                      int64_t n_out, float* alpha, float* beta, float* resid, float* kappa,
                      void* stream);
@@ -266,7 +270,9 @@ int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const i
  *   ESIM_THRESHOLDED: for the work-list items of a threshold call at t: emit
  *                     (px, py, t, sign dl) and replace the state with the
  *                     item's regression (alpha[i], beta[.., i], bxy and rmom
- *                     as for INIT), feat_t and t.
+ *                     as for INIT), feat_t and t.  n_out must be at least
+ *                     esim_plan_worklist_capacity (E_INVAL otherwise), so that
+ *                     every item a threshold call can list has its outputs.
  *   ESIM_EXHAUSTIVE:  every pixel: d = alpha - state.alpha (L_ref); if
  *                     |d| >= C emit sign d and set L_ref <- alpha.  At t = 0
  *                     (or for a fresh state) call ESIM_INIT first.
@@ -274,7 +280,7 @@ int esim_wlr_regress(esim_plan plan, int32_t t, const int64_t* worklist, const i
  *                     alpha = NULL; mode INIT with alpha = NULL stores y_t.
  * dl is the threshold call's output (THRESHOLDED and EXHAUSTIVE/RAW write the
  * compared change to it when non-NULL in the latter two).
- * Errors: E_INVAL (mode, missing buffers). */
+ * Errors: E_INVAL (mode, missing buffers, n_out). */
 int esim_events(esim_plan plan, int32_t t, int32_t mode, const int64_t* worklist,
                 const int32_t* count, float* dl, const float* alpha, const float* beta,
                 int64_t n_out, esim_events_buf* ev, void* stream);
@@ -311,7 +317,7 @@ int esim_step(esim_plan plan, int32_t t, int32_t mode, float* dl, esim_events_bu
  *   g_b[j]            += sum_items g_alpha sum_i (s_i r_i - lambda v^T E theta)
  *                        / W * w_i u_ij^2 / (h^2 b_j^3),  j < F + 2.
  * The window is recomputed, not stored.  Single-clip plans only; the clip's
- * features must stay below 4 GiB and r <= 25.  scratch: esim_backward_scratch_bytes.
+ * features and brightness must each stay below 4 GiB, and r <= 25.  scratch: esim_backward_scratch_bytes.
  * Errors: E_INVAL, E_CAPACITY (scratch too small), E_UNSUPPORTED. */
 size_t esim_backward_scratch_bytes(esim_plan plan, int64_t n);
 int esim_wlr_backward(esim_plan plan, const int64_t* items, int64_t n, const float* g_alpha,

@@ -26,6 +26,9 @@ THRESHOLDED, EXHAUSTIVE, RAW = 0, 1, 2
 # thresholded with Delta R = |R_hat - R| evaluated explicitly (eqs. 4 and 7):
 # R_hat over the last-event window, or over the current frame's window
 EXPLICIT_LAST, EXPLICIT_NEW = 3, 4
+# WLR+ESIM and ESIM with every crossing (eq. 1 applied to each level passed
+# between two frames, at interpolated times)
+EXHAUSTIVE_ALL, RAW_ALL = 5, 6
 
 
 def build(force: bool = False) -> str:
@@ -76,7 +79,7 @@ def _L():
         _lib.orc_cond.argtypes = [vp, i32]
         _lib.orc_cond.restype = dbl
         _lib.orc_run.argtypes = [vp, vp, i32, vp, i64, vp, vp, vp, vp, i64, vp, vp, vp, vp,
-                                 vp, vp, i32, vp, i32]
+                                 vp, vp, i32, vp, i32, vp]
         _lib.orc_run.restype = i64
         _lib.orc_backward.argtypes = [vp, vp, vp, i64, vp, vp, vp]
         _lib.orc_backward.restype = i32
@@ -263,11 +266,14 @@ def run(clip: Clip, p: Params, mode: int = THRESHOLDED, pixels: Optional[np.ndar
         nthreads: int = 0):
     """Event simulation (Sec. 1.1 eq. 1; Sec. 2.2 Prop. 1; Sec. 3 baselines;
     EXPLICIT_LAST / EXPLICIT_NEW: Sec. 2.2 with Delta R evaluated explicitly,
-    dl then holding sign * sqrt(Delta R)).
+    dl then holding sign * sqrt(Delta R); EXHAUSTIVE_ALL / RAW_ALL: the
+    baselines with every crossing, ESIM proper).
 
-    Returns dict(events=(x, y, t, p) int arrays in (t, py, px) order, count,
-    dl [T][npix] (if asked), nflag[T], state (alpha, beta[F][npix], xref, tref),
-    identity_err)."""
+    Returns dict(events=(x, y, t, p) int arrays in (t, py, px) order (the
+    crossings of one pixel-frame in time order), ts = event times in frame
+    units (the interpolated crossing times in the every-crossing modes), count,
+    dl [T][npix] (if asked), nflag[T], state (alpha, beta[F][npix], xref,
+    tref), identity_err)."""
     cp, b = _params(clip, p)
     HW = clip.H * clip.W
     if pixels is not None:
@@ -277,25 +283,31 @@ def run(clip: Clip, p: Params, mode: int = THRESHOLDED, pixels: Optional[np.ndar
         npix = HW
     if cap is None:
         cap = max(16, npix * clip.T)
-    ex = np.empty(cap, np.int32)
-    ey = np.empty(cap, np.int32)
-    et = np.empty(cap, np.int32)
-    ep = np.empty(cap, np.int8)
-    dl = np.empty((clip.T, npix)) if want_dl else None
-    nflag = np.empty(clip.T, np.int64)
-    st_a = np.empty(npix)
-    st_b = np.empty((clip.F, npix))
-    st_x = np.empty((clip.F, npix))
-    st_t = np.empty(npix, np.int32)
-    err = np.zeros(1)
-    n = _L().orc_run(ctypes.byref(clip._c), ctypes.byref(cp), mode, _p(pixels), npix,
-                     ex.ctypes.data, ey.ctypes.data, et.ctypes.data, ep.ctypes.data, cap,
-                     _p(dl), nflag.ctypes.data, st_a.ctypes.data, st_b.ctypes.data,
-                     st_x.ctypes.data, st_t.ctypes.data, 1 if check_identity else 0,
-                     err.ctypes.data, nthreads)
+    while True:
+        ex = np.empty(cap, np.int32)
+        ey = np.empty(cap, np.int32)
+        et = np.empty(cap, np.int32)
+        ep = np.empty(cap, np.int8)
+        ets = np.empty(cap, np.float64)
+        dl = np.empty((clip.T, npix)) if want_dl else None
+        nflag = np.empty(clip.T, np.int64)
+        st_a = np.empty(npix)
+        st_b = np.empty((clip.F, npix))
+        st_x = np.empty((clip.F, npix))
+        st_t = np.empty(npix, np.int32)
+        err = np.zeros(1)
+        n = _L().orc_run(ctypes.byref(clip._c), ctypes.byref(cp), mode, _p(pixels), npix,
+                         ex.ctypes.data, ey.ctypes.data, et.ctypes.data, ep.ctypes.data, cap,
+                         _p(dl), nflag.ctypes.data, st_a.ctypes.data, st_b.ctypes.data,
+                         st_x.ctypes.data, st_t.ctypes.data, 1 if check_identity else 0,
+                         err.ctypes.data, nthreads, ets.ctypes.data)
+        if n <= cap or mode not in (EXHAUSTIVE_ALL, RAW_ALL):
+            break
+        cap = int(n)        # several events per pixel-frame: run again with room for all
     m = min(n, cap)
     return dict(events=(ex[:m].copy(), ey[:m].copy(), et[:m].copy(), ep[:m].copy()), count=int(n),
-                dl=dl, nflag=nflag, state=dict(alpha=st_a, beta=st_b, xref=st_x, tref=st_t),
+                ts=ets[:m].copy(), dl=dl, nflag=nflag,
+                state=dict(alpha=st_a, beta=st_b, xref=st_x, tref=st_t),
                 identity_err=float(err[0]), pixels=pixels)
 
 
@@ -310,47 +322,3 @@ def backward(clip: Clip, p: Params, items: np.ndarray, galpha: np.ndarray):
     fails = _L().orc_backward(ctypes.byref(clip._c), ctypes.byref(cp), items.ctypes.data,
                               items.size, galpha.ctypes.data, gy.ctypes.data, gb.ctypes.data)
     return gy, gb, fails
-
-
-def esim_multi_crossing(L: np.ndarray, C: float, W: int):
-    """ESIM with every crossing (the event rule of Sec. 1.1 eq. 1 applied to each
-    level L_ref + k p C the brightness passes between two frames, the
-    brightness taken as linear between the frames):
-
-      at t = 0:  L_ref = L_last = L_0, no events
-      at t >= 1: d = L_t - L_ref, n = min(floor(|d| / C), 2^20), p = sign d; for k = 1..n
-                 an event (x, y, t, p) at the fractional time
-                 (t - 1) + (L_ref + k p C - L_last) / (L_t - L_last);
-                 L_ref <- L_ref + n p C (stored in FP32, like the state),
-                 L_last <- L_t.
-
-    L: [T][npix] values as stored (FP32); C and the arithmetic in FP64, each
-    product and sum rounded on its own.  Returns dict of
-    x, y, t, p, ts in (t, pixel, k) order."""
-    L = np.asarray(L, dtype=np.float32)
-    T, npix = L.shape
-    Cd = float(C)
-    Lref = L[0].copy()
-    Llast = L[0].copy()
-    xs, ys, ts_, ps, fts = [], [], [], [], []
-    for t in range(1, T):
-        cur = L[t]
-        d = cur.astype(np.float64) - Lref.astype(np.float64)
-        n = np.minimum(np.floor(np.abs(d) / Cd), 2.0 ** 20).astype(np.int64)   # cap of the option
-        pol = np.where(d > 0, 1, -1)
-        for q in np.nonzero(n >= 1)[0]:
-            pq = int(pol[q])
-            den = float(cur[q]) - float(Llast[q])
-            for k in range(1, int(n[q]) + 1):
-                level = float(Lref[q]) + k * (pq * Cd)
-                xs.append(q % W)
-                ys.append(q // W)
-                ts_.append(t)
-                ps.append(pq)
-                fts.append(np.float32((t - 1) + (level - float(Llast[q])) / den))
-        upd = n >= 1
-        Lref = np.where(upd, (Lref.astype(np.float64) + n * (pol * Cd)).astype(np.float32), Lref)
-        Llast = cur.copy()
-    return dict(x=np.array(xs, np.int32), y=np.array(ys, np.int32), t=np.array(ts_, np.int32),
-                p=np.array(ps, np.int8), ts=np.array(fts, np.float32), count=len(xs))
-

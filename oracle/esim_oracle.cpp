@@ -592,7 +592,9 @@ enum {
   ORC_EXHAUSTIVE = 1,
   ORC_RAW = 2,
   ORC_EXPLICIT_LAST = 3,
-  ORC_EXPLICIT_NEW = 4
+  ORC_EXPLICIT_NEW = 4,
+  ORC_EXHAUSTIVE_ALL = 5,
+  ORC_RAW_ALL = 6
 };
 
 // Event simulation over a whole clip (or a subset of pixels).
@@ -611,6 +613,16 @@ enum {
 //           Delta R >= C^2, with the sign of the translated plane's mean
 //           residual.  dl receives sign * sqrt(Delta R).
 //   mode 4: as mode 3 with R_hat over the window of the current frame.
+//   mode 5, 6: modes 1 and 2 with every crossing (ESIM proper, the event rule
+//           of eq. (1) applied to each level the brightness passes between
+//           two frames).  The compared brightness L is taken as linear between
+//           frames t - 1 and t.  With d = L_t - L_ref, n = floor(|d| / C) and
+//           p = sign d, the levels L_ref + k p C (k = 1..n) are events at the
+//           times (t - 1) + (L_ref + k p C - L_{t-1}) / (L_t - L_{t-1}); then
+//           L_ref <- L_ref + n p C (the last level passed, not L_t).  L_ref
+//           starts at L_0, so it stays on the lattice L_0 + C Z.  Everything
+//           in double precision, with no bound on n (a non-finite d fires
+//           nothing).
 //
 // pixels: optional list of pixel indices (ascending) to simulate; null = all.
 // Events are written in (t, py, px) order up to cap; the total count is
@@ -618,11 +630,14 @@ enum {
 // was compared with C (NaN at t = 0).  nflag (nullable, [T]) counts flagged
 // pixels per frame (mode 0) or events per frame.  st_alpha/st_beta/st_xref/
 // st_tref (nullable, [npix], [F][npix], [F][npix], [npix]) receive the final
-// state of mode 0; st_alpha receives L_ref in modes 1 and 2.
+// state of mode 0; st_alpha receives L_ref in modes 1, 2, 5 and 6.  ets
+// (nullable, [cap]) receives each event's time in frame units: t, or the
+// interpolated crossing time in modes 5 and 6.
 int64_t orc_run(const orc_clip* c, const orc_params* p, int mode, const int32_t* pixels,
                 int64_t npix_in, int32_t* ex, int32_t* ey, int32_t* et, int8_t* ep, int64_t cap,
                 double* dl, int64_t* nflag, double* st_alpha, double* st_beta, double* st_xref,
-                int32_t* st_tref, int check_identity, double* max_identity_err, int nthreads) {
+                int32_t* st_tref, int check_identity, double* max_identity_err, int nthreads,
+                double* ets) {
   Clip cl{c};
   const int F = c->F, D = F + 2, P = D + 1, T = c->T;
   const int64_t HW = static_cast<int64_t>(c->W) * c->H;
@@ -642,8 +657,11 @@ int64_t orc_run(const orc_clip* c, const orc_params* p, int mode, const int32_t*
     theta_full.assign(static_cast<size_t>(npix) * P, 0.0);
     Rref.assign(npix, 0.0);
   }
+  const bool every = mode == ORC_EXHAUSTIVE_ALL || mode == ORC_RAW_ALL;
   std::vector<signed char> fire(npix, 0);
   std::vector<double> value(npix, 0.0);
+  std::vector<double> cur(npix, 0.0), prev(npix, 0.0);   // every crossing: L_t, L_{t-1}
+  std::vector<int64_t> ncross(npix, 0);
   double max_err = 0.0;
   int64_t nev = 0;
 
@@ -707,7 +725,7 @@ int64_t orc_run(const orc_clip* c, const orc_params* p, int mode, const int32_t*
         }
       } else {
         double L;
-        if (mode == ORC_EXHAUSTIVE) {
+        if (mode == ORC_EXHAUSTIVE || mode == ORC_EXHAUSTIVE_ALL) {
           Fit fit = regress(cl, p, t, py, px, false, false);
           L = fit.theta[0];
         } else {
@@ -715,12 +733,21 @@ int64_t orc_run(const orc_clip* c, const orc_params* p, int mode, const int32_t*
         }
         if (t == 0) {
           ref[k] = L;
+          cur[k] = L;
           value[k] = NAN;
           continue;
         }
         const double d = L - ref[k];
         value[k] = d;
-        if (std::fabs(d) >= p->C) {
+        if (every) {
+          // levels passed; the events and the move of L_ref are taken in the
+          // ordered pass below, which needs L_{t-1}
+          const double q = std::floor(std::fabs(d) / p->C);
+          ncross[k] = (std::isfinite(q) && q >= 1.0) ? static_cast<int64_t>(q) : 0;
+          fire[k] = ncross[k] > 0 ? (d > 0 ? 1 : -1) : 0;
+          prev[k] = cur[k];
+          cur[k] = L;
+        } else if (std::fabs(d) >= p->C) {
           fire[k] = d > 0 ? 1 : -1;
           ref[k] = L;
         }
@@ -732,14 +759,26 @@ int64_t orc_run(const orc_clip* c, const orc_params* p, int mode, const int32_t*
       if (dl) dl[static_cast<int64_t>(t) * npix + k] = value[k];
       if (fire[k] == 0) continue;
       const int64_t pix = pix_of(k);
-      if (nev < cap) {
-        ex[nev] = static_cast<int32_t>(pix % c->W);
-        ey[nev] = static_cast<int32_t>(pix / c->W);
-        et[nev] = t;
-        ep[nev] = fire[k];
+      const int64_t n = every ? ncross[k] : 1;
+      for (int64_t j = 1; j <= n; ++j) {
+        if (nev < cap) {
+          ex[nev] = static_cast<int32_t>(pix % c->W);
+          ey[nev] = static_cast<int32_t>(pix / c->W);
+          et[nev] = t;
+          ep[nev] = fire[k];
+          if (ets) {
+            if (every) {
+              const double level = ref[k] + static_cast<double>(j) * fire[k] * p->C;
+              ets[nev] = (t - 1) + (level - prev[k]) / (cur[k] - prev[k]);
+            } else {
+              ets[nev] = t;
+            }
+          }
+        }
+        ++nev;
+        ++frame_events;
       }
-      ++nev;
-      ++frame_events;
+      if (every) ref[k] += static_cast<double>(n) * fire[k] * p->C;
     }
     if (nflag) nflag[t] = frame_events;
   }

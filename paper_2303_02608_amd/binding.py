@@ -43,7 +43,7 @@ class esim_params(ctypes.Structure):
                 ("h", ctypes.c_double), ("b", ctypes.c_double * MAX_D),
                 ("ridge", ctypes.c_double), ("precision", ctypes.c_int32),
                 ("kappa_fp64", ctypes.c_double), ("multi_crossing", ctypes.c_int32),
-                ("threshold", ctypes.c_int32)]
+                ("threshold", ctypes.c_int32), ("dt", ctypes.c_double)]
 
 
 class esim_state(ctypes.Structure):
@@ -132,12 +132,13 @@ class Params:
     def __init__(self, r: int, tr: int, C: float, h: float = 1.0,
                  b: Optional[Sequence[float]] = None, ridge: float = 1e-6,
                  precision: int = GRAM_F64, kappa_fp64: float = 1e6, multi_crossing: bool = False,
-                 threshold: int = THRESHOLD_CLOSED):
+                 threshold: int = THRESHOLD_CLOSED, dt: float = 1.0):
         self.r, self.tr, self.C, self.h = int(r), int(tr), float(C), float(h)
         self.b = None if b is None else [float(v) for v in b]
         self.ridge, self.precision, self.kappa_fp64 = float(ridge), int(precision), float(kappa_fp64)
         self.multi_crossing = bool(multi_crossing)
         self.threshold = int(threshold)
+        self.dt = float(dt)
 
     def struct(self, F: int) -> esim_params:
         b = [1.0] * (F + 2) if self.b is None else list(self.b)
@@ -145,7 +146,7 @@ class Params:
             raise ValueError(f"b needs F+2 = {F + 2} values")
         arr = (ctypes.c_double * MAX_D)(*(b + [1.0] * (MAX_D - len(b))))
         return esim_params(self.r, self.tr, self.C, self.h, arr, self.ridge, self.precision,
-                           self.kappa_fp64, int(self.multi_crossing), self.threshold)
+                           self.kappa_fp64, int(self.multi_crossing), self.threshold, self.dt)
 
 
 class State:

@@ -27,10 +27,12 @@ struct esim_plan_s {
   int lanes_dense = 1;     // lanes per regression item, dense launches
   int lanes_list = 16;     // lanes per regression item, work-list launches
   int blocks_per_cu = 4;   // persistent grid: 256 CUs x this many blocks
-  uint64_t max_feat_bytes = 0;
+  uint64_t max_feat_bytes = 0;   // largest feature array of a clip
+  uint64_t max_y_bytes = 0;      // largest brightness array of a clip
+  esim::DeviceShape shape;       // compute units and XCDs of the plan's device
   // work buffers of esim_step (allocated with the plan)
   void* step_mem = nullptr;
-  int64_t* xcd_bounds = nullptr;  // [5 lane counts][9] dense group bounds per XCD (device)
+  int64_t* xcd_bounds = nullptr;  // [5 lane counts][kMaxXcds + 1] dense group bounds per XCD (device)
   int64_t* step_wl = nullptr;     // [wl_capacity]
   int32_t* step_count = nullptr;  // [2]
   float* step_alpha = nullptr;    // [npix]
@@ -60,6 +62,21 @@ int hip_check(hipError_t e, const char* where) {
 
 }  // namespace
 
+namespace esim {
+
+bool query_device_shape(DeviceShape& out) {
+  int dev = 0, cus = 0, xccs = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return false;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+    return false;
+  if (hipDeviceGetAttribute(&xccs, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || xccs < 1) xccs = 1;
+  out.cus = cus;
+  out.xcds = xccs > kMaxXcds ? 1 : xccs;
+  return true;
+}
+
+}  // namespace esim
+
 namespace {
 
 int launch_plan_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int32_t* count,
@@ -83,11 +100,13 @@ int launch_plan_regress(esim_plan pl, int32_t t, const int64_t* worklist, const 
   a.resid = resid;
   a.kappa = kappa;
   a.update_state = update_state ? 1 : 0;
-  a.xcd_bounds = (!worklist && pl->nclips > 1) ? pl->xcd_bounds + 9 * esim::lanes_index(L) : nullptr;
+  a.xcd_bounds = (!worklist && pl->nclips > 1) ? pl->xcd_bounds + (esim::kMaxXcds + 1) * esim::lanes_index(L)
+                                                : nullptr;
+  a.nxcd = pl->shape.xcds;
   int max_r = 0;
   for (const auto& c : pl->host) max_r = std::max(max_r, static_cast<int>(c.r));
   return hip_check(esim::launch_regress(a, pl->F, pl->f16, pl->host[0].precision, L, pl->blocks_per_cu,
-                                        max_r, stream),
+                                        max_r, pl->shape, stream),
                    "regress");
 }
 
@@ -215,6 +234,10 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
         delete pl;
         return fail(ESIM_E_UNSUPPORTED, "all clips of a plan share the precision");
       }
+      if (!(p.dt > 0) || std::isinf(p.dt)) {
+        delete pl;
+        return fail(ESIM_E_INVAL, "dt must be positive and finite");
+      }
       if (p.threshold < ESIM_THRESHOLD_CLOSED || p.threshold > ESIM_THRESHOLD_NEW_WINDOW) {
         delete pl;
         return fail(ESIM_E_INVAL, "bad threshold");
@@ -241,6 +264,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
         cd.st_rmom = states[c].rmom;
       }
       cd.thr = p.threshold;
+      cd.dt = p.dt;
       cd.W = k.W;
       cd.H = k.H;
       cd.T = k.T;
@@ -283,11 +307,16 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
         return fail(ESIM_E_UNSUPPORTED, "the 2*tr+1 frames of a window must stay below 4 GiB");
       }
       pl->max_feat_bytes = std::max(pl->max_feat_bytes, fb);
+      pl->max_y_bytes = std::max(pl->max_y_bytes, static_cast<uint64_t>(k.T) * cd.HW * 4u);
       pl->host.push_back(cd);
     }
     // the compensated-FP32 instances exist for 4 and 16 lanes only
     if (params[0].precision == ESIM_GRAM_F32C) pl->lanes_dense = 4;
     pl->thr = params[0].threshold;
+    if (!esim::query_device_shape(pl->shape)) {
+      delete pl;
+      return fail(ESIM_E_HIP, "device attribute query failed");
+    }
     pl->npix = pix;
     pl->nblk = blk;
     pl->wl_capacity = wl;
@@ -304,7 +333,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     const size_t o_chunk = off;
     off = align(off + sizeof(int64_t) * ((blk + esim::kChunkBlocks - 1) / esim::kChunkBlocks));
     const size_t o_xcd = off;
-    off = align(off + sizeof(int64_t) * 5 * 9);
+    off = align(off + sizeof(int64_t) * 5 * (esim::kMaxXcds + 1));
     const size_t o_flags = off;
     off = align(off + sizeof(uint64_t) * blk * esim::kWavesPerBlock);
     const size_t o_pol = off;
@@ -324,11 +353,13 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     pl->ws.flags = reinterpret_cast<uint64_t*>(m + o_flags);
     pl->ws.pol = reinterpret_cast<uint64_t*>(m + o_pol);
     pl->ws.misc = reinterpret_cast<int64_t*>(m + o_misc);
-    // Dense launches of a multi-clip plan split the groups between the 8 XCDs
+    // Dense launches of a multi-clip plan split the groups between the XCDs
     // by work (window size x groups per clip) rather than by count, since a
     // clip's items cost in proportion to its window.
-    int64_t xb[5][9];
+    const int nx = pl->shape.xcds;
+    std::vector<int64_t> xb(5 * (esim::kMaxXcds + 1), 0);
     for (int q = 0; q < 5; ++q) {
+      int64_t* row = xb.data() + q * (esim::kMaxXcds + 1);
       double total = 0.0;
       std::vector<double> wc(nclips);
       std::vector<int64_t> gc(nclips);
@@ -338,10 +369,10 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
         wc[c] = static_cast<double>(2 * cd.r + 1) * (2 * cd.r + 1) * (2 * cd.tr + 1);
         total += wc[c] * static_cast<double>(gc[c]);
       }
-      xb[q][0] = 0;
-      xb[q][8] = grp[q];
-      for (int x = 1; x < 8; ++x) {
-        const double target = total * x / 8.0;
+      row[0] = 0;
+      row[nx] = grp[q];
+      for (int x = 1; x < nx; ++x) {
+        const double target = total * x / nx;
         double cum = 0.0;
         int64_t idx = grp[q];
         for (int c = 0; c < nclips; ++c) {
@@ -353,12 +384,13 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
           }
           cum += cw;
         }
-        xb[q][x] = std::max(xb[q][x - 1], idx);
+        row[x] = std::max(row[x - 1], idx);
       }
     }
     e = hipMemcpy(pl->dev, pl->host.data(), clip_bytes, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemset(m + o_bcount, 0, off - o_bcount);
-    if (e == hipSuccess) e = hipMemcpy(pl->xcd_bounds, xb, sizeof xb, hipMemcpyHostToDevice);
+    if (e == hipSuccess)
+      e = hipMemcpy(pl->xcd_bounds, xb.data(), sizeof(int64_t) * xb.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
       hipFree(pl->ws_mem);
@@ -446,8 +478,8 @@ int esim_wlr_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int
     if (!worklist && t < 0) return fail(ESIM_E_INVAL, "dense regression needs t >= 0");
     if (!worklist && n_out < pl->npix) return fail(ESIM_E_INVAL, "n_out < plan pixels");
     if (n_out < 0) return fail(ESIM_E_INVAL, "n_out < 0");
-    if (t < 0 && pl->max_feat_bytes >= (1ull << 32))
-      return fail(ESIM_E_UNSUPPORTED, "per-item frames need feature arrays below 4 GiB");
+    if (t < 0 && (pl->max_feat_bytes >= (1ull << 32) || pl->max_y_bytes >= (1ull << 32)))
+      return fail(ESIM_E_UNSUPPORTED, "per-item frames need feature and brightness arrays below 4 GiB");
     return launch_plan_regress(pl, t, worklist, count, n_out, alpha, beta, resid, kappa, false,
                                static_cast<hipStream_t>(stream));
   } catch (...) {
@@ -481,7 +513,10 @@ int esim_events(esim_plan pl, int32_t t, int32_t mode, const int64_t* worklist, 
     if (mode == ESIM_THRESHOLDED) {
       if (!worklist || !count || !dl || !alpha || !beta)
         return fail(ESIM_E_INVAL, "thresholded events need worklist, count, dl, alpha and beta");
-      if (n_out < 1) return fail(ESIM_E_INVAL, "n_out < 1");
+      // every item of the work list needs its model: the outputs must cover the
+      // largest work list a threshold call can produce
+      if (n_out < pl->wl_capacity)
+        return fail(ESIM_E_INVAL, "n_out < work-list capacity (esim_plan_worklist_capacity)");
       for (const auto& c : pl->host)
         if (!c.st_beta || !c.st_xref || !c.st_tref) return fail(ESIM_E_INVAL, "state incomplete");
       int rc = explicit_ok(pl);
@@ -636,13 +671,13 @@ int esim_wlr_backward(esim_plan pl, const int64_t* items, int64_t n, const float
     if (n < 0) return fail(ESIM_E_INVAL, "n < 0");
     if (n == 0) return ok();
     if (!items || !g_alpha || !g_y || !g_b) return fail(ESIM_E_INVAL, "null argument");
-    if (pl->max_feat_bytes >= (1ull << 32))
-      return fail(ESIM_E_UNSUPPORTED, "backward needs a feature array below 4 GiB");
+    if (pl->max_feat_bytes >= (1ull << 32) || pl->max_y_bytes >= (1ull << 32))
+      return fail(ESIM_E_UNSUPPORTED, "backward needs feature and brightness arrays below 4 GiB");
     if (esim::backward_gather_lds_bytes(pl->host[0]) > esim::kMaxGatherLds)
       return fail(ESIM_E_UNSUPPORTED, "backward supports window radii up to 25");
     const size_t need = esim::backward_scratch_bytes(pl->host[0], n);
     if (!scratch || scratch_bytes < need) return fail(ESIM_E_CAPACITY, "scratch too small");
-    esim::BackwardArgs a{pl->dev, &pl->host[0], items, n, g_alpha, g_y, g_b, scratch, scratch_bytes};
+    esim::BackwardArgs a{pl->dev, &pl->host[0], items, n, g_alpha, g_y, g_b, scratch, scratch_bytes, pl->shape};
     return hip_check(esim::launch_backward(a, static_cast<hipStream_t>(stream)), "backward");
   } catch (...) {
     return fail(ESIM_E_HIP, "exception");

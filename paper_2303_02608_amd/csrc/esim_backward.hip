@@ -65,7 +65,7 @@ map_items_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ 
 template <int F, int L, bool F16>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F <= 8 ? 2 : 1)))
 adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ items,
-               const float* __restrict__ g_alpha, BwdDev bd) {
+               const float* __restrict__ g_alpha, BwdDev bd, int nxcd) {
   constexpr int D = F + 2;
   constexpr int P = F + 3;
   constexpr int G = kWave / L;
@@ -76,7 +76,7 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
   const int64_t ngroups = (bd.n + G - 1) / G;
   const int r = C.r, tr = C.tr;
   const int span = 2 * r + 1;
-  GroupIter it_groups(ngroups);
+  GroupIter it_groups(ngroups, nxcd);
   int64_t g;
   while (it_groups.next(g)) {
     const int64_t i = g * G + slot;
@@ -281,7 +281,7 @@ __global__ void reduce_gb_final(BwdDev bd, int nblk, int D, double* g_b) {
   g_b[d] += s;
 }
 
-using AdjFn = void (*)(const ClipDev*, const int64_t*, const float*, BwdDev);
+using AdjFn = void (*)(const ClipDev*, const int64_t*, const float*, BwdDev, int);
 
 template <int F>
 AdjFn pick_adj(bool f16, bool wide) {
@@ -388,9 +388,11 @@ hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   const int L = wide ? kAdjLanesWide : kAdjLanes;
   const int G = kWave / L;
   int64_t blocks = ((a.n + G - 1) / G + kWavesPerBlock - 1) / kWavesPerBlock;
-  if (blocks > 2048) blocks = 2048;
-  blocks = (blocks + 7) / 8 * 8;   // a multiple of the 8 XCDs (see GroupIter)
-  hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a.clip, a.items, a.g_alpha, bd);
+  const int64_t cap = static_cast<int64_t>(a.dev.cus) * 8;
+  if (blocks > cap) blocks = cap;
+  blocks = (blocks + a.dev.xcds - 1) / a.dev.xcds * a.dev.xcds;   // a multiple of the XCDs (see GroupIter)
+  hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a.clip, a.items, a.g_alpha, bd,
+                     a.dev.xcds);
   const size_t lds = backward_gather_lds_bytes(hc);
   const int64_t gblocks = static_cast<int64_t>(hc.T) * hc.H * ((hc.W + kGatherTile - 1) / kGatherTile);
   hipLaunchKernelGGL(gather_kernel, dim3(static_cast<unsigned>(gblocks)), dim3(kGatherTile), lds, s, a.clip, bd,

@@ -228,16 +228,16 @@ scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, W
       for (int k = 1; k <= n; ++k) {
         const int64_t e = base + off + (k - 1);
         if (e >= ev.capacity) break;
-        // two roundings (no fused multiply-add), as the definition is written
-        const double level = __dadd_rn(static_cast<double>(Lref), __dmul_rn(static_cast<double>(k), step));
+        const double level = static_cast<double>(Lref) + static_cast<double>(k) * step;
         ev.x[e] = static_cast<int32_t>(p % C.W);
         ev.y[e] = static_cast<int32_t>(p / C.W);
         ev.t[e] = t;
         ev.p[e] = static_cast<int8_t>(pol);
         if (ev.clip) ev.clip[e] = cl;
-        if (ev.ts) ev.ts[e] = static_cast<float>((t - 1) + (level - static_cast<double>(Llast)) / den);
+        if (ev.ts) ev.ts[e] = static_cast<float>(((t - 1) + (level - static_cast<double>(Llast)) / den) * C.dt);
       }
-      C.st_alpha[p] = static_cast<float>(__dadd_rn(static_cast<double>(Lref), __dmul_rn(static_cast<double>(n), step)));
+      // the reference level is kept in FP32 like the rest of the state
+      C.st_alpha[p] = static_cast<float>(static_cast<double>(Lref) + static_cast<double>(n) * step);
     }
     if (in) C.st_last[p] = L;
     return;
@@ -258,7 +258,7 @@ scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, W
       ev.t[e] = t;
       ev.p[e] = pos ? 1 : -1;
       if (ev.clip) ev.clip[e] = cl;
-      if (ev.ts) ev.ts[e] = static_cast<float>(t);
+      if (ev.ts) ev.ts[e] = static_cast<float>(t * C.dt);
     }
   }
 }
@@ -325,7 +325,7 @@ __device__ void list_events_body(const ClipDev* __restrict__ clips, int nclips, 
       ev.t[e] = t;
       ev.p[e] = d > 0.0f ? 1 : -1;
       if (ev.clip) ev.clip[e] = cl;
-      if (ev.ts) ev.ts[e] = static_cast<float>(t);
+      if (ev.ts) ev.ts[e] = static_cast<float>(t * C.dt);
     }
     store_model(C, p, t, i, alpha, beta, n_out);
   }

@@ -38,7 +38,20 @@ struct ClipDev {
   float* st_bxy;           // [2][HW] coordinate components of beta (nullable)
   float* st_rmom;          // [2][HW] R and mean residual of the stored plane (nullable)
   int32_t thr;             // esim_threshold
+  double dt;               // time between frames (event times t * dt)
 };
+
+// Shape of the device a plan runs on, queried once when the plan is created:
+// compute units and the XCDs (L2 domains) they are grouped in.  Workgroups are
+// dispatched to the XCDs round-robin by block index.
+struct DeviceShape {
+  int cus = 1;
+  int xcds = 1;
+};
+constexpr int kMaxXcds = 32;
+// The current device's shape (hipDeviceAttributeMultiProcessorCount and
+// hipDeviceAttributeNumberOfXccs); returns false if a query fails.
+bool query_device_shape(DeviceShape& out);
 
 // Compaction workspace of a plan (device).
 struct Workspace {
@@ -148,7 +161,8 @@ struct RegressArgs {
   float* resid;
   float* kappa;
   int32_t update_state;     // write each item's model into its clip state (Sec. 2.2)
-  const int64_t* xcd_bounds;  // dense multi-clip launches: [9] group bounds per XCD (device)
+  const int64_t* xcd_bounds;  // dense multi-clip launches: [nxcd + 1] group bounds per XCD (device)
+  int32_t nxcd;               // XCDs of the device (group-to-XCD mapping)
 };
 
 // Regression launcher: picks the kernel instance for (F, dtype, precision)
@@ -164,7 +178,7 @@ struct RegressTable {
 };
 
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
-                          int blocks_per_cu, int max_r, hipStream_t s);
+                          int blocks_per_cu, int max_r, const DeviceShape& dev, hipStream_t s);
 int regress_supported_lanes(int F);
 bool regress_supports(int F, int lanes, int precision);
 
@@ -178,6 +192,7 @@ struct BackwardArgs {
   double* g_b;
   void* scratch;
   size_t scratch_bytes;
+  DeviceShape dev;
 };
 size_t backward_scratch_bytes(const ClipDev& hc, int64_t n);
 // LDS of the gather kernel (a staged input-row tile); at most 64 KiB is used.

@@ -61,15 +61,15 @@ bool regress_supports(int F, int lanes, int precision) {
 }
 
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
-                          int blocks_per_cu, int max_r, hipStream_t s) {
+                          int blocks_per_cu, int max_r, const DeviceShape& dev, hipStream_t s) {
   KernelFn fn = precision == ESIM_GRAM_F32C ? pick_c32(F, lanes, f16)
                 : (lanes == 16 && 2 * max_r + 1 <= 16 && !a.kappa) ? pick_onepass(F, f16)
                                                        : pick(F, lanes, f16);
   if (!fn) return hipErrorInvalidValue;
   int64_t blocks = (a.max_groups + kWavesPerBlock - 1) / kWavesPerBlock;
-  const int64_t cap = static_cast<int64_t>(256) * blocks_per_cu;
+  const int64_t cap = static_cast<int64_t>(dev.cus) * blocks_per_cu;
   if (blocks > cap) blocks = cap;
-  blocks = (blocks + 7) / 8 * 8;   // a multiple of the 8 XCDs (see GroupIter)
+  blocks = (blocks + dev.xcds - 1) / dev.xcds * dev.xcds;   // a multiple of the XCDs (see GroupIter)
   hipLaunchKernelGGL(fn, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a);
   return hipGetLastError();
 }

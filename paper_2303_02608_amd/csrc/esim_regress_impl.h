@@ -236,7 +236,7 @@ regress_kernel(RegressArgs a) {
   const int64_t n_items =
       a.items ? max(static_cast<int64_t>(0), min(static_cast<int64_t>(a.count[0]), a.n_out)) : 0;
   const int64_t ngroups = a.items ? (n_items + G - 1) / G : a.n_dense_groups;
-  GroupIter it(ngroups, a.items ? nullptr : a.xcd_bounds);
+  GroupIter it(ngroups, a.nxcd, a.items ? nullptr : a.xcd_bounds);
   int64_t g;
   while (it.next(g)) regress_group<F, L, F16, C32, ONE>(a, g, n_items);
 }

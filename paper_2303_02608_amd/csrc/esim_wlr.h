@@ -412,33 +412,33 @@ struct GramC {
 
 __host__ __device__ constexpr int tri(int i, int j) { return i * (i + 1) / 2 + j; }
 
-// Wave-group iteration with XCD affinity.  Workgroups are dispatched to the 8
-// XCDs round-robin by block index, so block b runs on XCD b % 8.  When the grid
-// is a multiple of 8 blocks, XCD x walks the contiguous x-th eighth of the
-// groups, which keeps spatially adjacent items (sharing window rows) in the
-// same L2; otherwise a plain grid stride is used.
+// Wave-group iteration with XCD affinity.  Workgroups are dispatched to the
+// nxcd XCDs round-robin by block index, so block b runs on XCD b % nxcd.  When
+// the grid is a multiple of nxcd blocks, XCD x walks a contiguous range of the
+// groups (the x-th of nxcd equal parts, or [xb[x], xb[x + 1]) when a split by
+// work is given), which keeps spatially adjacent items (sharing window rows)
+// in the same L2; otherwise a plain grid stride is used.
 struct GroupIter {
   int64_t g, end, step;
-  // xb (nullable): the groups of XCD x are [xb[x], xb[x + 1]) (a split by
-  // work rather than by count); otherwise XCD x takes the x-th eighth.
-  __device__ __forceinline__ GroupIter(int64_t ngroups, const int64_t* xb = nullptr) {
+  __device__ __forceinline__ GroupIter(int64_t ngroups, int nxcd, const int64_t* xb = nullptr) {
     const int64_t nblk = gridDim.x;
     const int64_t wib = threadIdx.x / kWave;            // wave in block
     const int64_t wpb = blockDim.x / kWave;
-    if (nblk >= 8 && nblk % 8 == 0) {
-      const int64_t x = blockIdx.x % 8;
+    const int64_t nx = nxcd;
+    if (nx > 1 && nblk >= nx && nblk % nx == 0) {
+      const int64_t x = blockIdx.x % nx;
       int64_t lo, hi;
       if (xb) {
         lo = xb[x];
         hi = min(ngroups, xb[x + 1]);
       } else {
-        const int64_t chunk = (ngroups + 7) / 8;
+        const int64_t chunk = (ngroups + nx - 1) / nx;
         lo = x * chunk;
         hi = min(ngroups, (x + 1) * chunk);
       }
-      g = lo + (blockIdx.x / 8) * wpb + wib;
+      g = lo + (blockIdx.x / nx) * wpb + wib;
       end = hi;
-      step = (nblk / 8) * wpb;
+      step = (nblk / nx) * wpb;
     } else {
       g = static_cast<int64_t>(blockIdx.x) * wpb + wib;
       end = ngroups;

@@ -29,7 +29,7 @@ MODES = ("thresholded", "exhaustive", "raw")
 
 class Simulator:
     def __init__(self, y: torch.Tensor, feat: torch.Tensor, params: B.Params,
-                 capacity: Optional[int] = None, want_dl: bool = True):
+                 capacity: Optional[int] = None, want_dl: bool = True, with_ts: Optional[bool] = None):
         T, F, H, W = feat.shape
         self.T, self.F, self.H, self.W = T, F, H, W
         self.HW = H * W
@@ -43,8 +43,9 @@ class Simulator:
         self.beta = torch.empty((F + 2, self.HW), dtype=torch.float32, device=dev)
         if capacity is None:
             capacity = min(T * self.HW, 1 << 26)
-        # every-crossing events carry their interpolated times
-        self.ev = B.Events(capacity, dev, with_ts=params.multi_crossing)
+        # event times t * dt (every-crossing events: their interpolated times);
+        # kept by default only for the every-crossing rule
+        self.ev = B.Events(capacity, dev, with_ts=params.multi_crossing if with_ts is None else with_ts)
         # per-frame flagged counts (only recorded when asked: it adds a copy per frame)
         self.flagged = torch.zeros(T, dtype=torch.int32, device=dev)
         self.graph = None

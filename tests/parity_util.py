@@ -112,3 +112,83 @@ def run_gpu(E, feat, params: B.Params, mode: str, capacity=None, keep_dl=False):
     out = sim.events()
     out["dl"] = dls
     return out, sim
+
+
+def compare_every_crossing(gpu: dict, orc: dict, L: np.ndarray, W: int, C: float, dt: float = 1.0,
+                           band: float = 1e-4, pixels=None, ts_abs: float = 1e-5,
+                           ts_rel: float = 5e-5):
+    """Every-crossing events (several per pixel-frame, interpolated times) of
+    the GPU against the oracle's (modes RAW_ALL / EXHAUSTIVE_ALL).
+
+    Per pixel, the (frame, polarity) sequences must be equal up to the first
+    frame where they differ; that frame is excused only if the oracle's
+    compared change |d| lies within `band` of a level k C (k >= 1), after which
+    the pixel is excused.  Before it, every event time must agree within
+    ts_abs * max(1, t) + ts_rel / |L_t - L_{t-1}| frames (the FP32 rounding of
+    the time, plus the brightness error over the frame's slope), scaled by dt.
+    L: [T][npix] the oracle's compared values (y, or its alpha) in the oracle's
+    pixel order.  Returns (n_compared, n_excused, failures, max time error)."""
+    ox, oy, ot, op = orc["events"]
+    dl = orc["dl"]
+    pix_list = np.asarray(orc["pixels"] if orc.get("pixels") is not None else np.arange(dl.shape[1]))
+    check = np.asarray(pix_list if pixels is None else pixels, dtype=np.int64)
+
+    def ordered(x, y, t, p, ts):
+        pix = y.astype(np.int64) * W + x
+        keep = np.isin(pix, check)
+        pix, t, p, ts = pix[keep], t[keep].astype(np.int64), p[keep].astype(np.int64), ts[keep]
+        o = np.lexsort((t, pix))          # stable: the crossings of a pixel-frame keep their order
+        return pix[o], t[o], p[o], ts[o]
+
+    gpix, gt, gp, gts = ordered(gpu["x"], gpu["y"], gpu["t"], gpu["p"], np.asarray(gpu["ts"], np.float64))
+    opix, ot_, op_, ots = ordered(ox, oy, ot, op, np.asarray(orc["ts"], np.float64) * dt)
+    npx = int(max(check.max(initial=0), 0)) + 1
+    cg = np.bincount(gpix, minlength=npx)
+    co = np.bincount(opix, minlength=npx)
+    same_n = cg == co
+    mg = same_n[gpix]
+    mo = same_n[opix]
+    # pixels with equal counts: events align one to one in the sorted order
+    bad = np.zeros(npx, bool)
+    mism = (gt[mg] != ot_[mo]) | (gp[mg] != op_[mo])
+    bad[gpix[mg][mism]] = True
+    bad |= ~same_n
+    # times of the pixels whose sequences agree completely
+    good_ev = ~bad[opix]
+    col = np.searchsorted(pix_list, opix[good_ev])
+    te = ot_[good_ev]
+    slope = np.abs(L[te, col] - L[te - 1, col])
+    err = np.abs(gts[~bad[gpix]] - ots[good_ev])
+    tol = dt * (ts_abs * np.maximum(1, te) + ts_rel / np.maximum(slope, 1e-30))
+    fails, excused = [], 0
+    max_err = float(err.max() / dt) if err.size else 0.0
+    for i in np.nonzero(err > tol)[0][:10]:
+        fails.append((int(opix[good_ev][i]), int(te[i]), "time", float(gts[~bad[gpix]][i]),
+                      float(ots[good_ev][i])))
+    # pixels whose sequences differ: the first differing frame must be in the band
+    for pix in np.nonzero(bad[check])[0]:
+        q = int(check[pix])
+        a = np.nonzero(gpix == q)[0]
+        b = np.nonzero(opix == q)[0]
+        n = 0
+        while n < a.size and n < b.size and gt[a[n]] == ot_[b[n]] and gp[a[n]] == op_[b[n]]:
+            n += 1
+        cand = ([gt[a[n]]] if n < a.size else []) + ([ot_[b[n]]] if n < b.size else [])
+        first = int(min(cand))
+        c = int(np.searchsorted(pix_list, q))
+        for i in range(n):
+            t = int(ot_[b[i]])
+            if t >= first:
+                break
+            e = abs(gts[a[i]] - ots[b[i]])
+            max_err = max(max_err, e / dt)
+            if e > dt * (ts_abs * max(1, t) + ts_rel / max(abs(L[t, c] - L[t - 1, c]), 1e-30)):
+                fails.append((q, t, "time", float(gts[a[i]]), float(ots[b[i]])))
+                break
+        d = abs(dl[first, c])
+        k = max(1.0, np.round(d / C))
+        if np.isfinite(d) and abs(d - k * C) <= band:
+            excused += 1
+        else:
+            fails.append((q, first, "events", float(d)))
+    return int(check.size), excused, fails, max_err

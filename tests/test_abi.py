@@ -84,7 +84,8 @@ def test_bad_shapes_and_params_are_rejected(lib):
               B.Params(r=5, tr=0, C=0.2, h=0.0), B.Params(r=5, tr=0, C=0.2, ridge=-1.0),
               B.Params(r=5, tr=0, C=0.2, b=[1.0] * 8 + [0.0]),
               B.Params(r=5, tr=0, C=0.2, precision=7), B.Params(r=5, tr=0, C=0.2, threshold=3),
-              B.Params(r=5, tr=0, C=0.2, threshold=-1)):
+              B.Params(r=5, tr=0, C=0.2, threshold=-1), B.Params(r=5, tr=0, C=0.2, dt=0.0),
+              B.Params(r=5, tr=0, C=0.2, dt=float("inf")), B.Params(r=5, tr=0, C=0.2, dt=float("nan"))):
         assert create(clip, p.struct(F)) == B.E_INVAL, vars(p)
     # mixed F across clips of one plan
     clips = (B.esim_clip * 2)(clip, B.esim_clip(64, 64, 4, 3, B.F32, 1, 1))

@@ -14,7 +14,7 @@ from paper_2303_02608_amd import binding as B
 from paper_2303_02608_amd import synth
 from paper_2303_02608_amd.autograd import wlr_alpha
 from paper_2303_02608_amd.simulator import Simulator
-from parity_util import MODE_ID, compare_events, say
+from parity_util import MODE_ID, compare_events, compare_every_crossing, say
 
 pytestmark = pytest.mark.gpu
 
@@ -59,62 +59,55 @@ def test_dvs_events_on_sampled_pixels(dvs, mode):
     assert orc["count"] > 0
 
 
-def _sorted_by_pixel_frame(t, pix, *cols):
-    """Stable order by (t, pixel): keeps the crossings of a pixel-frame in
-    their emitted order."""
-    o = np.lexsort((pix, t))
-    return [c[o] for c in (t, pix) + cols]
-
-
-@pytest.mark.parametrize("mode", ["raw", "exhaustive"])
-def test_dvs_multicrossing_on_sampled_pixels(dvs, mode):
-    """Every-crossing events on the whole DVS clip, launched as the
-    every-crossing workload launches them (the step entry point), against the
-    oracle's every-crossing rule on sampled pixels' whole histories: frames,
-    polarities and counts exactly, times exactly (both sides take them in
-    FP64 and round once to FP32).  The compared values are the GPU's own FP32
-    inputs of the rule (y for raw; for exhaustive the per-frame alpha of the
-    separate calls, whose events must equal the step's bit for bit)."""
+def test_dvs_raw_multicrossing_whole_clip(dvs):
+    """Every-crossing raw ESIM on the whole DVS clip, launched as the
+    every-crossing workload launches it (the step entry point), against the
+    oracle's every-crossing rule run from E on every pixel (the rule alone is
+    cheap on the host)."""
     cfg = dvs["cfg"]
-    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"], multi_crossing=True)
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"], multi_crossing=True, dt=cfg["dt"])
+    T, F, H, W = dvs["fn"].shape
+    say("DVS every-crossing raw, whole clip")
+    sim = Simulator(dvs["y"], dvs["feat"], p, capacity=1 << 27)
+    gpu = sim.run("raw")
+    assert 0 < gpu["count"] < sim.ev.capacity
+    oc = _oracle_clip(dvs)
+    orc = oracle.run(oc, oracle.Params(p.r, p.tr, p.C), oracle.RAW_ALL, want_dl=True)
+    n, exc, fails, err = compare_every_crossing(gpu, orc, oc.y.reshape(T, H * W), W, p.C, dt=p.dt)
+    say(f"DVS every-crossing raw: {n} pixels, gpu {gpu['count']} / oracle {orc['count']} events, "
+        f"excused {exc}, max time error {err:.2e} frames")
+    assert not fails, fails[:5]
+    assert exc <= n // 1000
+
+
+def test_dvs_exhaustive_multicrossing_on_sampled_pixels(dvs):
+    """Every-crossing WLR+ESIM on the whole DVS clip (step entry point) against
+    the oracle's every-crossing WLR+ESIM from E on sampled pixels' whole
+    histories (its own FP64 regressions of every frame)."""
+    cfg = dvs["cfg"]
+    p = B.Params(r=cfg["r"], tr=cfg["tr"], C=cfg["C"], multi_crossing=True, dt=cfg["dt"])
     T, F, H, W = dvs["fn"].shape
     HW = H * W
-    say(f"DVS every-crossing {mode}")
+    say("DVS every-crossing exhaustive")
     sim = Simulator(dvs["y"], dvs["feat"], p, capacity=1 << 27)
-    gpu = sim.run(mode)
+    gpu = sim.run("exhaustive")
     assert 0 < gpu["count"] < sim.ev.capacity
     rng = np.random.default_rng(17)
     gp = gpu["y"].astype(np.int64) * W + gpu["x"]
     fired = np.unique(gp)
     pix = np.unique(np.concatenate([rng.choice(HW, 64, replace=False),
                                     rng.choice(fired, min(64, fired.size), replace=False)]))
-    if mode == "raw":
-        L = dvs["y"].reshape(T, HW)[:, torch.from_numpy(pix).cuda()].cpu().numpy()
-    else:
-        sep = Simulator(dvs["y"], dvs["feat"], p, capacity=1 << 27)
-        idx = torch.from_numpy(pix).cuda()
-        cols = []
-        sep.ev.count.zero_()
-        for t in range(T):
-            B.regress(sep.plan, t, None, None, HW, sep.alpha, None)
-            cols.append(sep.alpha[idx].clone())
-            B.events(sep.plan, t, B.EXHAUSTIVE, sep.ev, dl=sep.dl, alpha=sep.alpha, n_out=HW)
-        torch.cuda.synchronize()
-        L = torch.stack(cols).cpu().numpy()
-        ev_sep = sep.events()
-        for k in ("x", "y", "t", "p", "ts"):
-            assert np.array_equal(ev_sep[k], gpu[k]), k
-        del sep
-    orc = oracle.esim_multi_crossing(L, p.C, 1)       # W = 1: the column index is y
-    keep = np.isin(gp, pix)
-    g = _sorted_by_pixel_frame(gpu["t"][keep].astype(np.int64), gp[keep], gpu["p"][keep], gpu["ts"][keep])
-    o = _sorted_by_pixel_frame(orc["t"].astype(np.int64), pix[orc["y"]], orc["p"], orc["ts"])
-    say(f"DVS every-crossing {mode}: {pix.size} sampled pixels, {orc['count']} oracle events, "
-        f"{gpu['count']} events in all")
+    oc = _oracle_clip(dvs)
+    op = oracle.Params(p.r, p.tr, p.C)
+    orc = oracle.run(oc, op, oracle.EXHAUSTIVE_ALL, pixels=pix, want_dl=True)
+    items = (np.arange(T, dtype=np.int64)[:, None] * HW + pix[None, :]).reshape(-1)
+    alpha = oracle.regress_items(oc, op, items)["theta"][:, 0].reshape(T, pix.size)
+    n, exc, fails, err = compare_every_crossing(gpu, orc, alpha, W, p.C, dt=p.dt, pixels=pix)
+    say(f"DVS every-crossing exhaustive: {n} sampled pixels, {orc['count']} oracle events, "
+        f"excused {exc}, max time error {err:.2e} frames")
     assert orc["count"] > pix.size
-    assert len(g[0]) == len(o[0])
-    for a, b in zip(g, o):
-        assert np.array_equal(a, b)
+    assert not fails, fails[:5]
+    assert exc <= 2
 
 
 @pytest.mark.parametrize("form", ["last", "new"])
