@@ -46,6 +46,9 @@ namespace {
 // re-solve of the same compensated Gram for items whose Hager condition
 // estimate exceeds kappa_fp64.  ONE selects the one-pass Gram (every lane
 // owns one window column).
+// Rows of window data in flight in the interior one-pass loop.
+constexpr int kRing = 3;
+
 template <int F, int L, bool F16, bool C32, bool ONE>
 __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, int64_t n_items) {
   constexpr int D = F + 2;
@@ -101,31 +104,61 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
       // the whole clip when items carry their own frame
       const int f0 = a.t >= 0 ? max(0, a.t - C.tr) : 0;
       const int f1 = a.t >= 0 ? min(C.T, a.t + C.tr + 1) : C.T;
-      // inactive lanes read a valid centre pixel of the resource window
+      // Interior waves: every item's window lies inside the image and the
+      // clip, so the window loop runs without per-row validity tests; lanes
+      // without an item then take the geometry of the first item (weights 0).
+      const int fr = active ? my_t : (a.t >= 0 ? a.t : 0);
+      const int prow = static_cast<int>(my_pix / C.W), pcol = static_cast<int>(my_pix - prow * C.W);
+      const bool inside = prow >= C.r && prow + C.r < C.H && pcol >= C.r && pcol + C.r < C.W &&
+                          fr - C.tr >= 0 && fr + C.tr < C.T;
+      const uint64_t act = __ballot(active);
+      const bool full = !C32 && __ballot(active && !inside) == 0;
+      int64_t gpix = active ? my_pix : 0;
+      int gfr = fr;
+      if (full) {
+        const int src = __ffsll(static_cast<unsigned long long>(act)) - 1;
+        const int64_t p0 = __shfl(my_pix, src);
+        const int t0 = __shfl(fr, src);
+        if (!active) {
+          gpix = p0;
+          gfr = t0;
+        }
+      }
       ItemGeom<F, F16, Real> geo;
-      make_geom(geo, C, active ? my_pix : 0, active ? my_t : (a.t >= 0 ? a.t : 0), f0, f1, active);
+      make_geom(geo, C, gpix, gfr, f0, f1, active);
 
       double th[P], rhs[P], Syy, iW, kap = 0.0;
       if constexpr (!C32) {
         Gram<F, double> gm;
-        if constexpr (ONE) {
-          // every lane owns one column (2r + 1 <= L, checked by the launcher)
-          gm.zero_onepass();
-          window_loop<F, L, F16, double>(
-              geo, j, [&](double) {},
-              [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-                gm.add_onepass(w, yd, v, vy);
-              },
-              [&](double vx) { gm.fold_onepass(vx); });
-        } else {
-          gm.zero_snap();
-          window_loop<F, L, F16, double>(
-              geo, j, [&](double) { gm.pass_begin_snap(); },
-              [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-                gm.add_onepass(w, yd, v, vy);
-              },
-              [&](double vx) { gm.pass_end_snap(vx); });
-        }
+        auto accumulate = [&](auto full_tag) {
+          constexpr bool FULL = decltype(full_tag)::value;
+          if constexpr (ONE) {
+            // every lane owns one column (2r + 1 <= L, checked by the launcher)
+            gm.zero_onepass();
+            auto add = [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+              gm.add_onepass(w, yd, v, vy);
+            };
+            if constexpr (FULL)
+              window_loop_ring<F, L, F16, kRing>(geo, j, [&](double) {}, add,
+                                                 [&](double vx) { gm.fold_onepass(vx); });
+            else
+              window_loop<F, L, F16, double, FULL>(geo, j, [&](double) {}, add,
+                                                   [&](double vx) { gm.fold_onepass(vx); });
+          } else {
+            gm.zero_snap();
+            auto add = [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+              gm.add_onepass(w, yd, v, vy);
+            };
+            if constexpr (FULL)
+              window_loop_ring<F, L, F16, kRing>(geo, j, [&](double) { gm.pass_begin_snap(); }, add,
+                                                 [&](double vx) { gm.pass_end_snap(vx); });
+            else
+              window_loop<F, L, F16, double, FULL>(geo, j, [&](double) { gm.pass_begin_snap(); }, add,
+                                                   [&](double vx) { gm.pass_end_snap(vx); });
+          }
+        };
+        if (full) accumulate(std::true_type{});
+        else accumulate(std::false_type{});
         gm.template lane_sum<L>();
         double M[P * (P + 1) / 2], anorm;
         iW = gram_solve<F, double>(gm, C, M, rhs, th, anorm);
@@ -179,9 +212,6 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
 
       // ---- outputs (the lanes of an item share the writes)
       if (active && a.update_state) {
-        // the pixel's reference model becomes this frame's: alpha, beta over
-        // the buffer channels, the feature vector and the frame (the values
-        // the event call would store from the outputs)
         if (j == 0) {
           C.st_alpha[my_pix] = static_cast<float>(th[0]);
           C.st_tref[my_pix] = my_t;

@@ -80,7 +80,16 @@ __device__ __forceinline__ void make_geom(ItemGeom<F, F16, Real>& g, const ClipD
 // The loop takes two rows per iteration (see the loop for an odd row count).
 // Row offsets advance by uniform (SGPR) amounts; only the validity test and
 // the select are per lane.
-template <int F, int L, bool F16, class Real, class PassBegin, class Sample, class PassEnd>
+//
+// FULL: the caller guarantees that the window of every lane's item lies
+// entirely inside the image and the clip (|dx|, |dy| <= r and |dt| <= tr all
+// valid; lanes without an item carry the geometry of one that has).  Then no
+// row needs a validity test or an address select: a lane's column offset is
+// fixed for the pass, the row offset is uniform, and only the lane's own
+// weight switch (no item, or the idle column of a lane group wider than the
+// window) remains.
+template <int F, int L, bool F16, class Real, bool FULL = false, class PassBegin, class Sample,
+          class PassEnd>
 __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int j,
                                             PassBegin&& pass_begin, Sample&& sample,
                                             PassEnd&& pass_end) {
@@ -88,7 +97,10 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
   constexpr Real K = static_cast<Real>(kHalfLog2e);
   const int r = g.r;
   const int span = 2 * r + 1;
-  const int nrows = (g.dt_hi - g.dt_lo + 1) * span;
+  // FULL: every lane's window spans 2 tr + 1 frames (a uniform count, so the
+  // loop bounds and row offsets below stay scalar)
+  const int nt = FULL ? 2 * g.tr + 1 : g.dt_hi - g.dt_lo + 1;
+  const int nrows = nt * span;
   const int npass = (span + L - 1) / L;
   // per-lane valid row range of the item (rows inside the image)
   const int dy_lo = -min(r, g.py), dy_hi = min(r, g.H - 1 - g.py);
@@ -96,7 +108,8 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
   const uint32_t FES = static_cast<uint32_t>(F) * g.HW * ES, HW4 = g.HW * 4u;
   for (int k = 0; k < npass; ++k) {
     const int dx = -r + j + k * L;
-    const int col = g.px + dx;
+    // FULL: an idle column reads the window's last column (weight 0)
+    const int col = g.px + (FULL ? min(dx, r) : dx);
     const bool col_ok = g.active && dx <= r && col >= 0 && col < g.W;
     const Real vx = static_cast<Real>(dx) * g.vx_step;
     const Real kx = K * vx * vx;
@@ -110,6 +123,23 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
                               static_cast<uint32_t>((g.py - r) * g.W + col)) * 4u;
     int ldt = 0, ldy = 0;          // next row to load, relative to (dt_lo, -r)
     auto load_row = [&](float& yv, float (&fv)[F]) -> bool {
+      if constexpr (FULL) {
+        // rows past the window (the pipeline's look-ahead) repeat the last
+        // row; their weights are never used
+        const bool in = ldt < nt;
+        const uint32_t lt = static_cast<uint32_t>(in ? ldt : nt - 1);
+        const uint32_t ly = static_cast<uint32_t>(in ? ldy : span - 1);
+        const uint32_t sof = lt * FES + ly * WES;
+        const uint32_t soy = lt * HW4 + ly * W4;
+        yv = ld_f32(g.ry, vy_base, soy);
+#pragma unroll
+        for (int f = 0; f < F; ++f) fv[f] = ld_feat<F16>(g.rf, vf_base, sof + f * g.HW * ES);
+        if (++ldy == span) {
+          ldy = 0;
+          ++ldt;
+        }
+        return col_ok;
+      }
       const int dy = ldy - r;
       const bool ok = (ldt <= g.dt_hi - g.dt_lo) & col_ok & (dy >= dy_lo) & (dy <= dy_hi);
       const uint32_t sof = static_cast<uint32_t>(ldt) * FES + static_cast<uint32_t>(ldy) * WES;
@@ -130,7 +160,7 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
       int dt, dy;
       bool ok;
     };
-    int cdt = g.dt_lo, cdy = -r;   // next row to weigh
+    int cdt = FULL ? -g.tr : g.dt_lo, cdy = -r;   // next row to weigh
     auto weigh = [&](float yv, const float (&fv)[F], bool ok, Wt& o) {
       o.dy = cdy;
       o.dt = cdt;
@@ -179,6 +209,86 @@ __device__ __forceinline__ void window_loop(const ItemGeom<F, F16, Real>& g, int
     if constexpr (kPeel) {
       if (q < nrows) use(wA);     // odd row count: the last row alone
     }
+    pass_end(vx);
+  }
+}
+
+// The window of one item whose window lies entirely inside the image and the
+// clip (the FULL case of window_loop), with a deeper load pipeline: a ring of
+// R rows in registers.  Each step weighs and accumulates the oldest row and
+// issues the loads of the row R ahead into its slot, so every load has R - 1
+// rows of work to arrive (the window rows of scattered work-list items often
+// miss the L2).  Same calls and order of samples as window_loop; sample()
+// receives dt = dy = 0 (unused by its callers).
+template <int F, int L, bool F16, int R, class PassBegin, class Sample, class PassEnd>
+__device__ __forceinline__ void window_loop_ring(const ItemGeom<F, F16, double>& g, int j,
+                                                 PassBegin&& pass_begin, Sample&& sample,
+                                                 PassEnd&& pass_end) {
+  constexpr uint32_t ES = ItemGeom<F, F16, double>::ES;
+  constexpr double K = kHalfLog2e;
+  const int r = g.r;
+  const int span = 2 * r + 1;
+  const int nt = 2 * g.tr + 1;
+  const int nrows = nt * span;
+  const int npass = (span + L - 1) / L;
+  const uint32_t WES = static_cast<uint32_t>(g.W) * ES, W4 = static_cast<uint32_t>(g.W) * 4u;
+  const uint32_t FES = static_cast<uint32_t>(F) * g.HW * ES, HW4 = g.HW * 4u;
+  for (int k = 0; k < npass; ++k) {
+    const int dx = -r + j + k * L;
+    const int col = g.px + min(dx, r);        // an idle column reads the last one (weight 0)
+    const bool col_ok = g.active && dx <= r;
+    const double vx = static_cast<double>(dx) * g.vx_step;
+    const double kx = K * vx * vx;
+    pass_begin(vx);
+    const uint32_t vf_base = (static_cast<uint32_t>(g.fc - g.tr) * F * g.HW +
+                              static_cast<uint32_t>((g.py - r) * g.W + col)) * ES;
+    const uint32_t vy_base = (static_cast<uint32_t>(g.fc - g.tr) * g.HW +
+                              static_cast<uint32_t>((g.py - r) * g.W + col)) * 4u;
+    int ldt = 0, ldy = 0;                     // next row to load (uniform)
+    auto load_next = [&](float& yv, float (&fv)[F]) {
+      // rows past the window repeat the last row; they are never consumed
+      const bool in = ldt < nt;
+      const uint32_t lt = static_cast<uint32_t>(in ? ldt : nt - 1);
+      const uint32_t ly = static_cast<uint32_t>(in ? ldy : span - 1);
+      yv = ld_f32(g.ry, vy_base, lt * HW4 + ly * W4);
+#pragma unroll
+      for (int f = 0; f < F; ++f) fv[f] = ld_feat<F16>(g.rf, vf_base, lt * FES + ly * WES + f * g.HW * ES);
+      if (++ldy == span) {
+        ldy = 0;
+        ++ldt;
+      }
+    };
+    int cdy = -r;                             // next row to consume (uniform)
+    auto consume = [&](float yv, const float (&fv)[F]) {
+      const double vy = static_cast<double>(cdy) * g.vy_step;
+      if (++cdy > r) cdy = -r;
+      double v[F], s0 = 0, s1 = 0;
+#pragma unroll
+      for (int f = 0; f < F; ++f) {
+        v[f] = fma(static_cast<double>(fv[f]), g.sf[2 + f], -g.xcs[f]);
+        if (f & 1) s1 = fma(v[f], v[f], s1);
+        else s0 = fma(v[f], v[f], s0);
+      }
+      const double arg = fma(s0 + s1, K, fma(K * vy, vy, kx));
+      const float e = __builtin_amdgcn_exp2f(static_cast<float>(arg));
+      sample(static_cast<double>(col_ok ? e : 0.0f), static_cast<double>(yv), v, vy, dx, 0, 0, col_ok);
+    };
+    float ys[R], fs[R][F];
+#pragma unroll
+    for (int i = 0; i < R; ++i) load_next(ys[i], fs[i]);
+    int q = 0;
+#pragma unroll 1
+    for (; q + R <= nrows; q += R) {
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        consume(ys[i], fs[i]);
+        load_next(ys[i], fs[i]);
+      }
+    }
+    // the last nrows - q rows sit in slots 0 .. nrows - q - 1
+#pragma unroll
+    for (int i = 0; i + 1 < R; ++i)
+      if (q + i < nrows) consume(ys[i], fs[i]);
     pass_end(vx);
   }
 }
