@@ -372,6 +372,25 @@ int esim_wlr_regress_bandwidth(esim_plan plan, int32_t t, const int64_t* worklis
  * Errors: E_INVAL (shapes, scales, null pointers), E_CAPACITY (scratch too
  * small), E_UNSUPPORTED (radius too wide). */
 size_t esim_nn_scratch_bytes(int32_t W, int32_t H, int32_t T);
+
+/* The same search for callers that cannot allocate device memory (code under
+ * hipGraph capture, tight serving loops): the occupancy bitmaps live in a
+ * fixed device array of ESIM_NN_STATIC_BYTES bytes inside the library, one
+ * per GPU, held until the process ends; nothing is allocated, by the library
+ * or by the caller.  Arguments as esim_nn_distances without the scratch.
+ * The first call on a device looks the array up (hipGetSymbolAddress);
+ * capture a graph only after one call on that device.  Every call on a GPU
+ * shares that GPU's array and clears the part it uses first: calls that
+ * overlap on one GPU (different streams, or graph replays in flight) race and
+ * must be serialised by the caller.
+ * Errors: as esim_nn_distances; E_CAPACITY when esim_nn_scratch_bytes(W, H, T)
+ * exceeds ESIM_NN_STATIC_BYTES; E_HIP if the array cannot be looked up. */
+#define ESIM_NN_STATIC_BYTES ((size_t)32 << 20)
+int esim_nn_distances_noalloc(const int32_t* src_x, const int32_t* src_y, const int32_t* src_t,
+                              const int8_t* src_p, int64_t ns, const int32_t* qry_x, const int32_t* qry_y,
+                              const int32_t* qry_t, const int8_t* qry_p, int64_t nq, int32_t W, int32_t H,
+                              int32_t T, double scale_x, double scale_y, double scale_t, double rmax, double* d,
+                              void* stream);
 int esim_nn_distances(const int32_t* src_x, const int32_t* src_y, const int32_t* src_t,
                       const int8_t* src_p, int64_t ns, const int32_t* qry_x, const int32_t* qry_y,
                       const int32_t* qry_t, const int8_t* qry_p, int64_t nq, int32_t W, int32_t H,

@@ -82,6 +82,9 @@ SIGNATURES = {
     "esim_nn_distances": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32,
                                  ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
                                  _vp, _vp, _sz, _vp]),
+    "esim_nn_distances_noalloc": (_i32, [_vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _i64, _i32, _i32, _i32,
+                                         ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                         _vp, _vp]),
     "esim_status_string": (ctypes.c_char_p, [_i32]),
     "esim_last_error": (ctypes.c_char_p, []),
     "esim_build_info": (ctypes.c_char_p, []),
@@ -330,6 +333,24 @@ def nn_distances(src: dict, qry: dict, W: int, H: int, T: int, rmax: float, scal
                                     _ptr(qry["p"]), nq, W, H, T, sx, sy, st, float(rmax), _ptr(d),
                                     _ptr(scratch), scratch.numel() * scratch.element_size(),
                                     _stream(stream)), "nn_distances")
+    return d
+
+
+NN_STATIC_BYTES = 32 << 20     # ESIM_NN_STATIC_BYTES
+
+
+def nn_distances_noalloc(src: dict, qry: dict, W: int, H: int, T: int, rmax: float, d: torch.Tensor,
+                         scales=None, stream=None) -> torch.Tensor:
+    """nn_distances with the library's fixed bitmap array: allocates nothing
+    (esim_nn_distances_noalloc); d (float64, one per query) is the output."""
+    sx, sy, st = scales if scales is not None else (1.0 / W, 1.0 / H, 1.0 / T)
+    nq = int(qry["x"].numel())
+    if d.dtype != torch.float64 or d.numel() < nq:
+        raise ValueError("d must be float64 with one value per query")
+    _check(load().esim_nn_distances_noalloc(_ptr(src["x"]), _ptr(src["y"]), _ptr(src["t"]), _ptr(src["p"]),
+                                            int(src["x"].numel()), _ptr(qry["x"]), _ptr(qry["y"]), _ptr(qry["t"]),
+                                            _ptr(qry["p"]), nq, W, H, T, sx, sy, st, float(rmax), _ptr(d),
+                                            _stream(stream)), "nn_distances_noalloc")
     return d
 
 

@@ -689,44 +689,82 @@ size_t esim_nn_scratch_bytes(int32_t W, int32_t H, int32_t T) {
   return esim::nn_scratch_bytes(W, H, T);
 }
 
+}  // extern "C"
+
+namespace {
+
+// Validation and marshalling shared by the two event-set comparison entry
+// points; scratch is the bitmap memory (caller's, or the library's fixed array).
+int nn_call(const int32_t* src_x, const int32_t* src_y, const int32_t* src_t, const int8_t* src_p, int64_t ns,
+            const int32_t* qry_x, const int32_t* qry_y, const int32_t* qry_t, const int8_t* qry_p, int64_t nq,
+            int32_t W, int32_t H, int32_t T, double scale_x, double scale_y, double scale_t, double rmax, double* d,
+            void* scratch, size_t scratch_bytes, bool fixed, void* stream) {
+  if (W < 1 || H < 1 || T < 1 || ns < 0 || nq < 0) return fail(ESIM_E_INVAL, "bad shape or count");
+  if (!(scale_x > 0) || !(scale_y > 0) || !(scale_t > 0) || !(rmax >= 0) || std::isinf(rmax))
+    return fail(ESIM_E_INVAL, "scales must be positive and rmax finite and >= 0");
+  if ((ns > 0 && (!src_x || !src_y || !src_t || !src_p)) || (nq > 0 && (!qry_x || !qry_y || !qry_t || !qry_p || !d)))
+    return fail(ESIM_E_INVAL, "null event array");
+  const size_t need = esim::nn_scratch_bytes(W, H, T);
+  if (fixed) {
+    if (need > ESIM_NN_STATIC_BYTES)
+      return fail(ESIM_E_CAPACITY, "the bitmaps of this W x H x T exceed the fixed array (ESIM_NN_STATIC_BYTES)");
+    if (!esim::nn_static_scratch(&scratch)) return fail(ESIM_E_HIP, "lookup of the fixed bitmap array failed");
+  } else if (!scratch || scratch_bytes < need) {
+    return fail(ESIM_E_CAPACITY, "scratch too small");
+  }
+  const double ex = std::floor(rmax / scale_x), ey = std::floor(rmax / scale_y), et = std::floor(rmax / scale_t);
+  if (ex >= 4096) return fail(ESIM_E_UNSUPPORTED, "rmax spans 4096 columns or more");
+  esim::NnArgs a{};
+  a.sx = src_x;
+  a.sy = src_y;
+  a.st = src_t;
+  a.sp = src_p;
+  a.ns = ns;
+  a.qx = qry_x;
+  a.qy = qry_y;
+  a.qt = qry_t;
+  a.qp = qry_p;
+  a.nq = nq;
+  a.W = W;
+  a.H = H;
+  a.T = T;
+  a.scale_x = scale_x;
+  a.scale_y = scale_y;
+  a.scale_t = scale_t;
+  a.rmax = rmax;
+  a.rx = static_cast<int>(std::min<double>(ex, W));
+  a.ry = static_cast<int>(std::min<double>(ey, H));
+  a.rt = static_cast<int>(std::min<double>(et, T));
+  a.d = d;
+  a.scratch = scratch;
+  return hip_check(esim::launch_nn(a, static_cast<hipStream_t>(stream)), "nn_distances");
+}
+
+}  // namespace
+
+extern "C" {
+
 int esim_nn_distances(const int32_t* src_x, const int32_t* src_y, const int32_t* src_t, const int8_t* src_p,
                       int64_t ns, const int32_t* qry_x, const int32_t* qry_y, const int32_t* qry_t,
                       const int8_t* qry_p, int64_t nq, int32_t W, int32_t H, int32_t T, double scale_x,
                       double scale_y, double scale_t, double rmax, double* d, void* scratch,
                       size_t scratch_bytes, void* stream) {
   try {
-    if (W < 1 || H < 1 || T < 1 || ns < 0 || nq < 0) return fail(ESIM_E_INVAL, "bad shape or count");
-    if (!(scale_x > 0) || !(scale_y > 0) || !(scale_t > 0) || !(rmax >= 0) || std::isinf(rmax))
-      return fail(ESIM_E_INVAL, "scales must be positive and rmax finite and >= 0");
-    if ((ns > 0 && (!src_x || !src_y || !src_t || !src_p)) || (nq > 0 && (!qry_x || !qry_y || !qry_t || !qry_p || !d)))
-      return fail(ESIM_E_INVAL, "null event array");
-    if (!scratch || scratch_bytes < esim::nn_scratch_bytes(W, H, T)) return fail(ESIM_E_CAPACITY, "scratch too small");
-    const double ex = std::floor(rmax / scale_x), ey = std::floor(rmax / scale_y), et = std::floor(rmax / scale_t);
-    if (ex >= 4096) return fail(ESIM_E_UNSUPPORTED, "rmax spans 4096 columns or more");
-    esim::NnArgs a{};
-    a.sx = src_x;
-    a.sy = src_y;
-    a.st = src_t;
-    a.sp = src_p;
-    a.ns = ns;
-    a.qx = qry_x;
-    a.qy = qry_y;
-    a.qt = qry_t;
-    a.qp = qry_p;
-    a.nq = nq;
-    a.W = W;
-    a.H = H;
-    a.T = T;
-    a.scale_x = scale_x;
-    a.scale_y = scale_y;
-    a.scale_t = scale_t;
-    a.rmax = rmax;
-    a.rx = static_cast<int>(std::min<double>(ex, W));
-    a.ry = static_cast<int>(std::min<double>(ey, H));
-    a.rt = static_cast<int>(std::min<double>(et, T));
-    a.d = d;
-    a.scratch = scratch;
-    return hip_check(esim::launch_nn(a, static_cast<hipStream_t>(stream)), "nn_distances");
+    return nn_call(src_x, src_y, src_t, src_p, ns, qry_x, qry_y, qry_t, qry_p, nq, W, H, T, scale_x, scale_y,
+                   scale_t, rmax, d, scratch, scratch_bytes, false, stream);
+  } catch (...) {
+    return fail(ESIM_E_HIP, "exception");
+  }
+}
+
+int esim_nn_distances_noalloc(const int32_t* src_x, const int32_t* src_y, const int32_t* src_t,
+                              const int8_t* src_p, int64_t ns, const int32_t* qry_x, const int32_t* qry_y,
+                              const int32_t* qry_t, const int8_t* qry_p, int64_t nq, int32_t W, int32_t H,
+                              int32_t T, double scale_x, double scale_y, double scale_t, double rmax, double* d,
+                              void* stream) {
+  try {
+    return nn_call(src_x, src_y, src_t, src_p, ns, qry_x, qry_y, qry_t, qry_p, nq, W, H, T, scale_x, scale_y,
+                   scale_t, rmax, d, nullptr, 0, true, stream);
   } catch (...) {
     return fail(ESIM_E_HIP, "exception");
   }

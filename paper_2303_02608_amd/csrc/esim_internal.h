@@ -216,6 +216,10 @@ struct NnArgs {
 };
 size_t nn_scratch_bytes(int W, int H, int T);
 hipError_t launch_nn(const NnArgs& a, hipStream_t s);
+// Device address of the fixed bitmap array of esim_nn_distances_noalloc on
+// the current device (ESIM_NN_STATIC_BYTES bytes), looked up on the first call
+// per device; false if the lookup fails.
+bool nn_static_scratch(void** out);
 
 // Explicit Delta R threshold (dense over the plan's pixels at frame t): fills
 // dl and the flag/polarity ballots and block counts of the compaction

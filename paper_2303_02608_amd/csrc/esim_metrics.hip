@@ -19,9 +19,17 @@
 //                        neighbour within rmax.
 #include <cmath>
 #include <cstdint>
+#include <mutex>
 
 #include "esim.h"
 #include "esim_internal.h"
+
+// Occupancy bitmaps of esim_nn_distances_noalloc: a fixed device array, so that
+// call allocates nothing.  Each GPU the library runs on holds its own copy
+// until the process ends.  In host code this name is a host-side stand-in, not
+// a device address: the device address is obtained once per device with
+// hipGetSymbolAddress (nn_static_scratch) and only that address is used.
+static __device__ __align__(256) uint32_t scratch[ESIM_NN_STATIC_BYTES / sizeof(uint32_t)];
 
 namespace esim {
 namespace {
@@ -129,6 +137,22 @@ unsigned grid_for(int64_t n) {
 }
 
 }  // namespace
+
+bool nn_static_scratch(void** out) {
+  constexpr int kMaxDevices = 64;
+  static std::mutex mu;
+  static void* addr[kMaxDevices] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return false;
+  std::lock_guard<std::mutex> lock(mu);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return false;
+    addr[dev] = p;
+  }
+  *out = addr[dev];
+  return true;
+}
 
 size_t nn_scratch_bytes(int W, int H, int T) {
   const int64_t wpr = (static_cast<int64_t>(W) + 31) / 32;
