@@ -10,7 +10,6 @@ failure."""
 from __future__ import annotations
 
 import sys
-from collections import defaultdict
 
 import numpy as np
 import torch
@@ -38,44 +37,45 @@ def oracle_clip(E: np.ndarray, feat: np.ndarray):
     return oracle.Clip(oracle.log_brightness(E), feat)
 
 
-def events_by_pixel(x, y, t, p, W):
-    d = defaultdict(list)
-    for a, b, c, q in zip(x, y, t, p):
-        d[int(b) * W + int(a)].append((int(c), int(q)))
-    return d
-
-
 def compare_events(gpu: dict, orc: dict, W: int, C: float, band: float = 1e-4,
                    pixels=None):
-    """Returns (n_compared_pixels, n_excused, failures[list])."""
+    """Returns (n_compared_pixels, n_excused, failures[list]).  Vectorised:
+    pixels whose (frame, polarity) histories agree exactly are settled with
+    array operations; only the others are examined one by one."""
     ox, oy, ot, op = orc["events"]
-    g = events_by_pixel(gpu["x"], gpu["y"], gpu["t"], gpu["p"], W)
-    o = events_by_pixel(ox, oy, ot, op, W)
     dl = orc["dl"]                      # [T][npix] in the oracle's pixel order
-    pix_list = orc["pixels"] if orc.get("pixels") is not None else np.arange(dl.shape[1])
-    col = {int(p): k for k, p in enumerate(pix_list)}
+    pix_list = np.asarray(orc["pixels"] if orc.get("pixels") is not None else np.arange(dl.shape[1]))
+    check = np.asarray(pix_list if pixels is None else pixels, dtype=np.int64)
+
+    def ordered(x, y, t, p):
+        pix = np.asarray(y, np.int64) * W + np.asarray(x, np.int64)
+        keep = np.isin(pix, check)
+        pix, t, p = pix[keep], np.asarray(t, np.int64)[keep], np.asarray(p, np.int64)[keep]
+        o = np.lexsort((t, pix))
+        return pix[o], t[o], p[o]
+
+    gpix, gt, gp = ordered(gpu["x"], gpu["y"], gpu["t"], gpu["p"])
+    opix, ot_, op_ = ordered(ox, oy, ot, op)
+    npx = int(check.max(initial=0)) + 1
+    cg = np.bincount(gpix, minlength=npx)
+    co = np.bincount(opix, minlength=npx)
+    bad = cg != co
+    same = ~bad
+    mg, mo = same[gpix], same[opix]
+    mism = (gt[mg] != ot_[mo]) | (gp[mg] != op_[mo])
+    bad[gpix[mg][mism]] = True
     fails, excused = [], 0
-    check = pix_list if pixels is None else pixels
-    for pix in check:
-        pix = int(pix)
-        ge, oe = g.get(pix, []), o.get(pix, [])
-        if ge == oe:
-            continue
-        # first differing frame
-        gi = {t: q for t, q in ge}
-        oi = {t: q for t, q in oe}
-        frames = sorted(set(gi) | set(oi))
-        first = None
-        for t in frames:
-            if gi.get(t) != oi.get(t):
-                first = t
-                break
-        d = dl[first, col[pix]]
+    for q in check[bad[check]]:
+        q = int(q)
+        gi = {int(t): int(pp) for t, pp in zip(gt[gpix == q], gp[gpix == q])}
+        oi = {int(t): int(pp) for t, pp in zip(ot_[opix == q], op_[opix == q])}
+        first = min(t for t in set(gi) | set(oi) if gi.get(t) != oi.get(t))
+        d = dl[first, int(np.searchsorted(pix_list, q))]
         if np.isfinite(d) and abs(abs(d) - C) <= band:
             excused += 1
         else:
-            fails.append((pix, first, gi.get(first), oi.get(first), float(d)))
-    return len(check), excused, fails
+            fails.append((q, first, gi.get(first), oi.get(first), float(d)))
+    return int(check.size), excused, fails
 
 
 def run_gpu(E, feat, params: B.Params, mode: str, capacity=None, keep_dl=False):
