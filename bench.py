@@ -125,86 +125,118 @@ def _graph(fn):
 
 
 def workload_precision(args, B, synth, Simulator):
-    """X1: F = 10 FP16 features at 1920x1080, r = 10, tr = 2."""
+    """X1: 1920x1080, all 500 frames, F = 10 FP16 features, r = 10, tr = 2:
+    the FP64 Gram (production path) and the compensated FP32 Gram with an FP64
+    re-solve above the equilibrated condition bound 1e6."""
     import torch
     from paper_2303_02608_amd import autotune
     cfg = synth.config_spec(4)
     spec = cfg["spec"]
-    T = 24
+    T = spec.T if args.precision_frames is None else args.precision_frames
     t0 = time.time()
-    d = synth.make_clip(spec, device="cuda", frames=range(T))
-    y = B.log_brightness(d["E"])
-    feat = d["feat"]
-    torch.cuda.synchronize()
-    log(f"generated {spec.W}x{spec.H}x{T} (of {spec.T}) F={spec.F} f16 in {time.time() - t0:.1f}s")
-    _, F, H, W = feat.shape
+    H, W, F = spec.H, spec.W, spec.F
+    y = torch.empty((T, H, W), dtype=torch.float32, device="cuda")
+    feat = torch.empty((T, F, H, W), dtype=torch.float16, device="cuda")
+    step = 25
+    for a in range(0, T, step):
+        b = min(T, a + step)
+        d = synth.make_clip(spec, device="cuda", frames=range(a, b))
+        B.log_brightness(d["E"], out=y[a:b])
+        feat[a:b].copy_(d["feat"])
+        del d
+        torch.cuda.synchronize()
+        log(f"generated frames {a}..{b - 1} of {T} ({time.time() - t0:.0f}s)")
     HW = H * W
     r, tr, C = cfg["r"], cfg["tr"], cfg["C"]
     tc = T // 2
     om = omega_sizes(np.arange(HW) % W, np.arange(HW) // W, np.full(HW, tc), W, H, T, r, tr)
     fl = regress_flops(om, F).sum()
-    out = {"workload": f"precision {W}x{H}, {T} of {spec.T} frames, F={F} f16, r={r}, tr={tr}, C={C}"}
-    alphas = {}
+    out = {"workload": f"precision {W}x{H}x{T}, F={F} f16, r={r}, tr={tr}, C={C}",
+           "generate_s": round(time.time() - t0, 1)}
     for name, prec, kb in (("fp64", B.GRAM_F64, float("inf")), ("f32c", B.GRAM_F32C, 1e6)):
-        p = B.Params(r=r, tr=tr, C=C, precision=prec, kappa_fp64=kb)
+        p = B.Params(r=r, tr=tr, C=C, precision=prec, kappa_fp64=kb, dt=cfg["dt"])
         sim = Simulator(y, feat, p)
         plan = sim.plan
         sched = autotune.tune(plan)
         a = torch.empty(HW, device="cuda")
-        b = torch.empty((plan.D, HW), device="cuda")
-        K = torch.empty(HW, device="cuda") if prec == B.GRAM_F32C else None
-        ms = _time_ms(lambda: B.regress(plan, tc, None, None, HW, a, b, None, K), 3)
-        alphas[name] = a.clone()
+        bb = torch.empty((plan.D, HW), device="cuda")
+        ms = _time_ms(lambda: B.regress(plan, tc, None, None, HW, a, bb), 3)
         row = {"dense_regress_ms": round(ms, 3), "dense_tflops": round(fl / (ms * 1e-3) / 1e12, 2),
                "dense_frac": round(fl / (ms * 1e-3) / 1e12 / PEAK_ALU_TFLOPS, 4),
                "schedule": list(sched)}
-        if K is not None:
-            k = K.cpu().numpy()
-            row["fp64_resolve_share"] = round(float(np.mean(~(k <= kb))), 5)
+        if prec == B.GRAM_F32C:
+            # share of regressions re-solved in FP64 (equilibrated kappa-hat
+            # above the bound), every pixel of the first, middle and last frames
+            K = torch.empty(HW, device="cuda")
+            shares = {}
+            for t in (tr, tc, T - 1 - tr):
+                B.regress(plan, t, None, None, HW, a, bb, None, K)
+                k = K.cpu().numpy()
+                shares[str(t)] = round(float(np.mean(~(k <= kb))), 6)
+                if t == tc:
+                    row["kappa_hat_quantiles"] = {q: float(np.quantile(k[np.isfinite(k)], q))
+                                                  for q in (0.5, 0.9, 0.99, 0.999)}
+            row["fp64_resolve_share"] = shares
         run = _graph(lambda: sim.enqueue("thresholded"))
-        ms_t = _time_ms(run, 3)
+        ms_t = _time_ms(run, 2)
         ev = sim.events()
         row.update(thresholded_ms=round(ms_t, 3), pixel_frames_per_s=round(T * HW / (ms_t * 1e-3), 1),
-                   events=ev["count"], events_per_s=round(ev["count"] / (ms_t * 1e-3), 1))
+                   events=ev["count"], events_per_s=round(ev["count"] / (ms_t * 1e-3), 1),
+                   flagged_fraction=round(ev["count"] / ((T - 1) * HW), 5))
         out[name] = row
         log(f"precision {name}: dense {ms:.3f} ms, thresholded {ms_t:.3f} ms")
-        del sim
-    da = (alphas["f32c"] - alphas["fp64"]).abs() / alphas["fp64"].abs().clamp(min=1.0)
-    out["f32c_vs_fp64_alpha_rel_err_max"] = float(da.max())
+        del sim, plan
+        torch.cuda.empty_cache()
     return out
 
 
 def workload_batch(args, B, synth, Simulator):
-    """X2: the 32-clip batch, frames scaled to about 2e8 pixel-frames."""
+    """X2: the 32-clip batch at its full size (every clip's T frames), one plan
+    and one persistent work-list launch per step over all clips, against the
+    same clips converted one plan each; per-clip flagged fraction reported."""
     import torch
     from paper_2303_02608_amd.simulator import BatchSimulator
-    specs = synth.batch_specs(32, seed=5000, max_pixel_frames=2e8)
+    specs = synth.batch_specs(32, seed=5000)
     t0 = time.time()
     ys, feats, params = [], [], []
-    for c in specs:
+    for k, c in enumerate(specs):
         d = synth.make_clip(c["spec"], device="cuda")
         ys.append(B.log_brightness(d["E"]))
         feats.append(d["feat"])
-        params.append(B.Params(r=c["r"], tr=c["tr"], C=c["C"]))
+        params.append(B.Params(r=c["r"], tr=c["tr"], C=c["C"], dt=c["dt"]))
         del d
-    torch.cuda.synchronize()
+        torch.cuda.synchronize()
+        log(f"generated clip {k}: {c['spec'].W}x{c['spec'].H}x{c['spec'].T} ({time.time() - t0:.0f}s)")
     pf = sum(int(f.shape[0]) * f.shape[2] * f.shape[3] for f in feats)
     log(f"generated {len(specs)} clips, {pf / 1e6:.1f} M pixel-frames in {time.time() - t0:.1f}s")
     bs = BatchSimulator(ys, feats, params)
     run = _graph(bs.enqueue)
     ms_b = _time_ms(run, 3)
-    ev_b = bs.ev.host()["count"]
+    got = bs.ev.host()
+    ev_b = got["count"]
+    log(f"batch: {ms_b:.2f} ms batched")
+    clips = []
+    for k, (c, f) in enumerate(zip(specs, feats)):
+        T, F, H, W = f.shape
+        n = int((got["clip"] == k).sum())
+        clips.append({"W": W, "H": H, "T": T, "spp": c["spec"].spp, "r": c["r"],
+                      "phi_target": round(c["phi_target"], 4),
+                      "phi": round(n / max(1, (T - 1) * H * W), 4), "events": n})
+    del bs
     sims = [Simulator(y, f, p) for y, f, p in zip(ys, feats, params)]
     runs = [_graph(lambda s=s: s.enqueue("thresholded")) for s in sims]
     ms_s = _time_ms(lambda: [r() for r in runs], 3)
     ev_s = sum(s.events()["count"] for s in sims)
     log(f"batch: {ms_b:.2f} ms batched, {ms_s:.2f} ms one by one")
-    return {"workload": f"batch of {len(specs)} clips, {pf} pixel-frames (frames scaled to 2e8)",
+    phis = [c["phi"] for c in clips]
+    return {"workload": f"batch of {len(specs)} clips, {pf} pixel-frames (every clip at its full length)",
+            "pixel_frames": pf,
             "batched_ms": round(ms_b, 3), "batched_pixel_frames_per_s": round(pf / (ms_b * 1e-3), 1),
             "one_by_one_ms": round(ms_s, 3),
             "one_by_one_pixel_frames_per_s": round(pf / (ms_s * 1e-3), 1),
             "events": ev_b, "events_one_by_one": ev_s,
-            "batched_speedup": round(ms_s / ms_b, 3)}
+            "batched_speedup": round(ms_s / ms_b, 3),
+            "phi_range": [min(phis), max(phis)], "clips": clips}
 
 
 def workload_diff(args, B, synth, Simulator):
@@ -598,6 +630,8 @@ def main():
                                            "bandwidth", "multicrossing"),
                     default="dvs",
                     help="dvs (default, the contract line) or one of the extension workloads")
+    ap.add_argument("--precision-frames", type=int, default=None,
+                    help="frames of the precision workload (default: all 500)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (the "
                          "known-size reference for HBM counter calibration)")

@@ -246,13 +246,16 @@ int esim_wlr_threshold(esim_plan plan, int32_t t, float* dl, int64_t* worklist,
  *   beta[d * n_out + i] (nullable) = gradient over the D = F + 2 features,
  *                       coordinates first,
  *   resid[i] (nullable) = R of eq. (4) at the minimiser,
- *   kappa[i] (nullable) = kappa-hat: ||A||_1 times Hager's estimate of
- *                       ||A^{-1}||_1 on the Cholesky factor, A the W-normalised
- *                       Gram plus ridge in bandwidth-scaled regressors
- *                       u_j / (h b_j) (the unscaled system when all bandwidths
- *                       are 1); a lower bound of the 1-norm condition number.
- *                       With ESIM_GRAM_F32C it is the FP32 estimate that
- *                       decides the FP64 re-solve (re-solved iff it exceeds
+ *   kappa[i] (nullable) = kappa-hat: the 1-norm condition number of the
+ *                       equilibrated system As = S^-1 A S^-1 (S^2 = diag(A),
+ *                       unit diagonal), ||As||_1 times Hager's estimate of
+ *                       ||As^{-1}||_1 from A's Cholesky factor; A is the
+ *                       W-normalised Gram plus ridge in bandwidth-scaled
+ *                       regressors u_j / (h b_j).  A lower bound of
+ *                       kappa_1(As), which (van der Sluis) governs the
+ *                       rounding error of the Cholesky solve.  With
+ *                       ESIM_GRAM_F32C it is the FP32 estimate that decides
+ *                       the FP64 re-solve (re-solved iff it exceeds
  *                       kappa_fp64 or is not finite).
  * Errors: E_INVAL (null outputs, n_out too small for dense mode),
  * E_UNSUPPORTED (t < 0 with a clip of 4 GiB or more of features or brightness). */

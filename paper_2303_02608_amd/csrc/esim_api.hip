@@ -82,7 +82,9 @@ namespace {
 int launch_plan_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int32_t* count,
                         int64_t n_out, float* alpha, float* beta, float* resid, float* kappa,
                         bool update_state, hipStream_t stream) {
-  const int L = worklist ? pl->lanes_list : pl->lanes_dense;
+  // the condition estimate of the FP64 Gram comes from a one-lane instance
+  const bool kappa_f64 = kappa && pl->host[0].precision == ESIM_GRAM_F64;
+  const int L = kappa_f64 ? 1 : worklist ? pl->lanes_list : pl->lanes_dense;
   if (!esim::regress_supports(pl->F, L, pl->host[0].precision))
     return fail(ESIM_E_UNSUPPORTED, "no kernel instance for this F, lane count and precision");
   esim::RegressArgs a{};

@@ -175,6 +175,7 @@ struct RegressTable {
   KernelFn general[5][2] = {};
   KernelFn onepass[2] = {};
   KernelFn c32[2][2] = {};
+  KernelFn kappa[2] = {};      // FP64 Gram with the condition estimate, one lane per item
 };
 
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,

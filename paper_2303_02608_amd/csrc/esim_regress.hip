@@ -62,8 +62,12 @@ bool regress_supports(int F, int lanes, int precision) {
 
 hipError_t launch_regress(const RegressArgs& a, int F, bool f16, int precision, int lanes,
                           int blocks_per_cu, int max_r, const DeviceShape& dev, hipStream_t s) {
+  // the condition estimate (FP64 Gram) has an instance of its own, one lane
+  // per item (the caller sizes the groups for one lane)
+  const RegressTable* tab = table(F);
   KernelFn fn = precision == ESIM_GRAM_F32C ? pick_c32(F, lanes, f16)
-                : (lanes == 16 && 2 * max_r + 1 <= 16 && !a.kappa) ? pick_onepass(F, f16)
+                : a.kappa ? (tab ? tab->kappa[f16] : nullptr)
+                : (lanes == 16 && 2 * max_r + 1 <= 16) ? pick_onepass(F, f16)
                                                        : pick(F, lanes, f16);
   if (!fn) return hipErrorInvalidValue;
   int64_t blocks = (a.max_groups + kWavesPerBlock - 1) / kWavesPerBlock;

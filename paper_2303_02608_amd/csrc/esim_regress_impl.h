@@ -49,7 +49,10 @@ namespace {
 // Rows of window data in flight in the interior one-pass loop.
 constexpr int kRing = 3;
 
-template <int F, int L, bool F16, bool C32, bool ONE>
+// KAPPA: the instance that writes the condition estimate (FP64 Gram, one lane
+// per item); the estimate's code stays out of the other instances, whose
+// register budget it would raise.
+template <int F, int L, bool F16, bool C32, bool ONE, bool KAPPA>
 __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, int64_t n_items) {
   constexpr int D = F + 2;
   constexpr int P = F + 3;
@@ -104,15 +107,18 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
       // the whole clip when items carry their own frame
       const int f0 = a.t >= 0 ? max(0, a.t - C.tr) : 0;
       const int f1 = a.t >= 0 ? min(C.T, a.t + C.tr + 1) : C.T;
-      // Interior waves: every item's window lies inside the image and the
-      // clip, so the window loop runs without per-row validity tests; lanes
-      // without an item then take the geometry of the first item (weights 0).
+      // Interior waves of the one-pass (work-list) instances: every item's
+      // window lies inside the image and the clip, so the window loop runs
+      // without per-row validity tests; lanes without an item then take the
+      // geometry of the first item (weights 0).  The other instances keep the
+      // checked loop only: a second loop variant costs them registers (many
+      // spills at F = 10, one wave per SIMD).
       const int fr = active ? my_t : (a.t >= 0 ? a.t : 0);
       const int prow = static_cast<int>(my_pix / C.W), pcol = static_cast<int>(my_pix - prow * C.W);
       const bool inside = prow >= C.r && prow + C.r < C.H && pcol >= C.r && pcol + C.r < C.W &&
                           fr - C.tr >= 0 && fr + C.tr < C.T;
       const uint64_t act = __ballot(active);
-      const bool full = !C32 && __ballot(active && !inside) == 0;
+      const bool full = ONE && !C32 && __ballot(active && !inside) == 0;
       int64_t gpix = active ? my_pix : 0;
       int gfr = fr;
       if (full) {
@@ -130,44 +136,29 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
       double th[P], rhs[P], Syy, iW, kap = 0.0;
       if constexpr (!C32) {
         Gram<F, double> gm;
-        auto accumulate = [&](auto full_tag) {
-          constexpr bool FULL = decltype(full_tag)::value;
-          if constexpr (ONE) {
-            // every lane owns one column (2r + 1 <= L, checked by the launcher)
-            gm.zero_onepass();
-            auto add = [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-              gm.add_onepass(w, yd, v, vy);
-            };
-            if constexpr (FULL)
-              window_loop_ring<F, L, F16, kRing>(geo, j, [&](double) {}, add,
-                                                 [&](double vx) { gm.fold_onepass(vx); });
-            else
-              window_loop<F, L, F16, double, FULL>(geo, j, [&](double) {}, add,
-                                                   [&](double vx) { gm.fold_onepass(vx); });
-          } else {
-            gm.zero_snap();
-            auto add = [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-              gm.add_onepass(w, yd, v, vy);
-            };
-            if constexpr (FULL)
-              window_loop_ring<F, L, F16, kRing>(geo, j, [&](double) { gm.pass_begin_snap(); }, add,
-                                                 [&](double vx) { gm.pass_end_snap(vx); });
-            else
-              window_loop<F, L, F16, double, FULL>(geo, j, [&](double) { gm.pass_begin_snap(); }, add,
-                                                   [&](double vx) { gm.pass_end_snap(vx); });
-          }
+        auto add = [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+          gm.add_onepass(w, yd, v, vy);
         };
-        if (full) accumulate(std::true_type{});
-        else accumulate(std::false_type{});
+        if constexpr (ONE) {
+          // every lane owns one column (2r + 1 <= L, checked by the launcher)
+          gm.zero_onepass();
+          if (full)
+            window_loop_ring<F, L, F16, kRing>(geo, j, [&](double) {}, add,
+                                               [&](double vx) { gm.fold_onepass(vx); });
+          else
+            window_loop<F, L, F16, double>(geo, j, [&](double) {}, add, [&](double vx) { gm.fold_onepass(vx); });
+        } else {
+          gm.zero_snap();
+          window_loop<F, L, F16, double>(geo, j, [&](double) { gm.pass_begin_snap(); }, add,
+                                         [&](double vx) { gm.pass_end_snap(vx); });
+        }
         gm.template lane_sum<L>();
         double M[P * (P + 1) / 2], anorm;
         iW = gram_solve<F, double>(gm, C, M, rhs, th, anorm);
         Syy = gm.Syy;
-        // the one-pass instances leave the estimate to the general ones (the
-        // launcher never picks them when kappa is requested), which keeps
-        // their register budget within two waves per SIMD
-        if constexpr (!ONE) {
-          if (a.kappa) kap = anorm * hager_inv_norm1<P, double>(M);
+        if constexpr (KAPPA) {
+          equilibrate_factor<P, double>(M);
+          kap = anorm * hager_inv_norm1<P, double>(M);
         } else {
           (void)anorm;
         }
@@ -185,6 +176,7 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
         gc.values(g32);
         float M32[P * (P + 1) / 2], r32[P], t32[P], an32;
         iW = gram_solve<F, float>(g32, C, M32, r32, t32, an32);
+        equilibrate_factor<P, float>(M32);
         kap = static_cast<double>(an32) * static_cast<double>(hager_inv_norm1<P, float>(M32));
         const bool fallback = !(kap <= C.kappa_fp64);
         Syy = g32.Syy;
@@ -236,7 +228,7 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
             for (int i = 1; i < P; ++i) bb = fma(th[i] * C.c2[i - 1], th[i], bb);
             a.resid[idx_out] = static_cast<float>(Syy * iW - tg - C.ridge * bb);
           }
-          if (a.kappa) a.kappa[idx_out] = static_cast<float>(kap);
+          if (a.kappa && (KAPPA || C32)) a.kappa[idx_out] = static_cast<float>(kap);
         }
         if (a.beta) {
 #pragma unroll
@@ -258,7 +250,7 @@ constexpr int regress_waves_per_simd() {
   return (!C32 && F <= 8) ? 2 : 1;
 }
 
-template <int F, int L, bool F16, bool C32, bool ONE = false>
+template <int F, int L, bool F16, bool C32, bool ONE = false, bool KAPPA = false>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(regress_waves_per_simd<F, C32>())))
 regress_kernel(RegressArgs a) {
   constexpr int G = kWave / L;
@@ -268,7 +260,7 @@ regress_kernel(RegressArgs a) {
   const int64_t ngroups = a.items ? (n_items + G - 1) / G : a.n_dense_groups;
   GroupIter it(ngroups, a.nxcd, a.items ? nullptr : a.xcd_bounds);
   int64_t g;
-  while (it.next(g)) regress_group<F, L, F16, C32, ONE>(a, g, n_items);
+  while (it.next(g)) regress_group<F, L, F16, C32, ONE, KAPPA>(a, g, n_items);
 }
 
 }  // namespace

@@ -25,6 +25,8 @@ void ESIM_CAT(regress_table_, ESIM_REGRESS_F)(RegressTable& t) {
   t.general[4][1] = regress_kernel<F, 16, true, false>;
   t.onepass[0] = regress_kernel<F, 16, false, false, true>;
   t.onepass[1] = regress_kernel<F, 16, true, false, true>;
+  t.kappa[0] = regress_kernel<F, 1, false, false, false, true>;
+  t.kappa[1] = regress_kernel<F, 1, true, false, false, true>;
   // the compensated-FP32 variant is compiled for the feature counts of the
   // workloads (7 and 10) and for the default lane counts
 #if ESIM_REGRESS_F == 7 || ESIM_REGRESS_F == 10

@@ -608,7 +608,8 @@ __device__ __forceinline__ void cholesky_inplace(Real (&M)[P * (P + 1) / 2]) {
 // Assembles the W-normalised system in scaled units (unknowns alpha, beta_x,
 // beta_y, beta_f..), adds the scaled ridge, factors it in place (packed lower
 // Cholesky) and solves for theta.  Returns 1/W.  anorm1 receives the 1-norm of
-// the assembled matrix (for the condition estimate).
+// the equilibrated matrix S^-1 A S^-1 (S^2 = diag(A), unit diagonal), for the
+// condition estimate (equilibrate_factor, hager_inv_norm1).
 template <int F, class Real>
 __device__ __forceinline__ Real gram_solve(const Gram<F, Real>& G, const ClipDev& C,
                                            Real (&M)[(F + 3) * (F + 4) / 2], Real (&rhs)[F + 3],
@@ -640,25 +641,57 @@ __device__ __forceinline__ Real gram_solve(const Gram<F, Real>& G, const ClipDev
       }
     }
   }
+  Real isd[P];
+#pragma unroll
+  for (int i = 0; i < P; ++i) isd[i] = Real(1) / sqrt(M[tri(i, i)]);
   anorm1 = 0;
 #pragma unroll
   for (int c = 0; c < P; ++c) {
     Real cs = 0;
 #pragma unroll
-    for (int i = 0; i < P; ++i) cs += fabs(i >= c ? M[tri(i, c)] : M[tri(c, i)]);
-    anorm1 = fmax(anorm1, cs);
+    for (int i = 0; i < P; ++i) cs += fabs(i >= c ? M[tri(i, c)] : M[tri(c, i)]) * isd[i];
+    anorm1 = fmax(anorm1, cs * isd[c]);
   }
   cholesky_inplace<P, Real>(M);
   chol_solve<P, Real>(M, rhs, th);
   return iW;
 }
 
+__device__ __forceinline__ double rsq_approx(double x) { return __builtin_amdgcn_rsq(x); }
+__device__ __forceinline__ float rsq_approx(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rcp_approx(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// Turns the packed Cholesky factor of A (diagonal slots holding 1 / L_ii) into
+// the factor of the equilibrated As = S^-1 A S^-1, S^2 = diag(A): row i of L
+// divided by S_i, with A_ii = sum_k L_ik^2 read off the factor itself.  In
+// place; M is no longer A's factor afterwards.  By van der Sluis the rounding
+// error of the Cholesky solve is governed by kappa(As), not kappa(A), whose
+// diagonal spans the ridge (a constant feature) to 1.
+template <int P, class Real>
+__device__ __forceinline__ void equilibrate_factor(Real (&M)[P * (P + 1) / 2]) {
+#pragma unroll
+  for (int i = 0; i < P; ++i) {
+    // A_ii = L_ii^2 + sum_k L_ik^2, with L_ii = 1 / M_ii (the slot's value)
+    const Real lii = rcp_approx(M[tri(i, i)]);
+    Real s = lii * lii;
+#pragma unroll
+    for (int k = 0; k < i; ++k) s += M[tri(i, k)] * M[tri(i, k)];
+    // an estimate needs no correctly rounded root: the hardware reciprocal
+    // square root (about 1 ulp) keeps this short
+    const Real isd = rsq_approx(s), sd = s * isd;
+#pragma unroll
+    for (int k = 0; k < i; ++k) M[tri(i, k)] *= isd;
+    M[tri(i, i)] *= sd;
+  }
+}
+
 // Estimate of ||A^{-1}||_1 for a symmetric positive definite A from its
-// Cholesky factor, after Hager (1984) with Higham's refinements (1988, the
-// scheme of LAPACK's xLACN2): power-like steps on sign vectors, at most five
-// solves with unit vectors, then an extra test vector with alternating signs.
-// kappa_1 is estimated as ||A||_1 times this; the estimate never exceeds the
-// true value.
+// packed Cholesky factor, after Hager (1984) with Higham's refinements (1988,
+// the scheme of LAPACK's xLACN2): power-like steps on sign vectors, at most
+// five solves with unit vectors, then an extra test vector with alternating
+// signs.  kappa_1 is estimated as ||A||_1 times this; the estimate never
+// exceeds the true value.
 template <int P, class Real>
 __device__ __forceinline__ Real hager_inv_norm1(const Real (&M)[P * (P + 1) / 2]) {
   Real b[P], x[P], z[P], xi[P];

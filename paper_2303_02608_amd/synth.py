@@ -160,10 +160,51 @@ def config_spec(index: int) -> dict:
     raise ValueError(f"no single-clip workload {index}")
 
 
+# Flagged fraction of the thresholded method (C = 0.15, r = 5, tr = 1) against
+# the disc count, measured on 640x360 clips with textured discs (texture cell
+# 2.5 px, radius 0.08-0.2 of the short side) at two motion tiers: translation
+# and rim speed 0.3-0.8 px/frame ("slow") and 2-4 px/frame ("fast").  The
+# batch workload draws a target fraction per clip and reads the disc count
+# off these curves (log-log interpolation); the fraction actually reached is
+# an outcome, reported per clip.
+_PHI_DISCS = (1, 3, 8, 20, 40)
+_PHI_SLOW = (0.012, 0.0225, 0.041, 0.098, 0.12)
+_PHI_FAST = (0.031, 0.054, 0.10, 0.23, 0.30)
+
+
+def _discs_for(phi: float, curve) -> float:
+    lp = [math.log(v) for v in curve]
+    ln = [math.log(v) for v in _PHI_DISCS]
+    x = math.log(phi)
+    if x <= lp[0]:
+        return 1.0
+    for k in range(len(lp) - 1):
+        if x <= lp[k + 1]:
+            a = (x - lp[k]) / (lp[k + 1] - lp[k])
+            return math.exp(ln[k] + a * (ln[k + 1] - ln[k]))
+    a = (x - lp[-2]) / (lp[-1] - lp[-2])          # beyond the last point: extend
+    return math.exp(ln[-2] + a * (ln[-1] - ln[-2]))
+
+
+def batch_scene(phi: float) -> dict:
+    """Scene parameters aimed at a flagged fraction phi: slow discs up to 10 %,
+    fast discs above; beyond 40 fast discs the radius grows instead of the
+    count (coverage rises with the radius squared)."""
+    if phi <= 0.10:
+        return dict(n_discs=max(1, int(round(_discs_for(phi, _PHI_SLOW)))), speed=(0.3, 0.8),
+                    radius=(0.08, 0.2))
+    n = _discs_for(phi, _PHI_FAST)
+    if n <= 40:
+        return dict(n_discs=int(round(n)), speed=(2.0, 4.0), radius=(0.08, 0.2))
+    g = min(1.6, math.sqrt(n / 40.0))
+    return dict(n_discs=40, speed=(2.0, 4.0), radius=(0.08 * g, 0.2 * g))
+
+
 def batch_specs(n_clips: int = 32, seed: int = 5000,
                 max_pixel_frames: Optional[float] = None) -> list:
     """Clip list of the batching workload: W ~ U{128..1280}, H ~ U{128..720},
-    T ~ U{30..300}, spp ~ U{2..16}, r ~ U{5..9}, Tr = 1, F = 7, C = 0.15.
+    T ~ U{30..300}, spp ~ U{2..16}, r ~ U{5..9}, Tr = 1, F = 7, C = 0.15, and a
+    target flagged fraction phi log-uniform in [1 %, 40 %] (batch_scene).
 
     ``max_pixel_frames`` optionally scales T down (keeping every other draw)
     so a reduced variant fits a test budget."""
@@ -175,11 +216,12 @@ def batch_specs(n_clips: int = 32, seed: int = 5000,
         T = 30 + int(u[2] * (300 - 30 + 1))
         spp = 2 + int(u[3] * 15)
         r = 5 + int(u[4] * 5)
-        n_discs = 2 + int(u[5] * 14)
-        out.append(dict(spec=ClipSpec(W=W, H=H, T=T, spp=spp, F=7, n_discs=n_discs,
-                                      speed=(0.05, 0.6), ang_speed=(0.002, 0.02),
-                                      disc_cell=6.0 + 6.0 * u[6], seed=seed + i),
-                        r=r, tr=1, C=0.15, dt=1e-3))
+        phi = math.exp(math.log(0.01) + u[5] * (math.log(0.40) - math.log(0.01)))
+        sc = batch_scene(phi)
+        out.append(dict(spec=ClipSpec(W=W, H=H, T=T, spp=spp, F=7, n_discs=sc["n_discs"],
+                                      speed=sc["speed"], rim_speed=sc["speed"], radius=sc["radius"],
+                                      disc_cell=2.5, seed=seed + i),
+                        r=r, tr=1, C=0.15, dt=1e-3, phi_target=phi))
     if max_pixel_frames is not None:
         tot = sum(c["spec"].W * c["spec"].H * c["spec"].T for c in out)
         if tot > max_pixel_frames:
