@@ -284,6 +284,31 @@ def workload_diff(args, B, synth, Simulator):
             "adjoint_flop_model": "forward F_reg + 60 FLOP per window sample"}
 
 
+EDGE_PX = 1.5    # an event within this distance of a disc outline is at a moving edge
+
+
+def edge_split(spec, ev, d, r, taus):
+    """Events split by where they are: "edge" (the pixel centre within EDGE_PX
+    of a disc outline at frame t or t - 1, so a moving outline crossed or
+    touched the pixel), "near" (within r: the regression window reaches an
+    outline) and "interior".  Per class: the events and the share whose
+    nearest same-polarity counterpart is closer than each tau (precision for
+    generated events, recall for reference events)."""
+    import torch
+    from paper_2303_02608_amd import synth
+    t, x, y = ev["t"].long(), ev["x"].long(), ev["y"].long()
+    dist = torch.minimum(synth.boundary_distance(spec, t, x, y),
+                         synth.boundary_distance(spec, (t - 1).clamp(min=0), x, y))
+    out = {}
+    for name, m in (("edge", dist <= EDGE_PX), ("near", (dist > EDGE_PX) & (dist <= r)),
+                    ("interior", dist > r)):
+        n = int(m.sum())
+        out[name] = {"events": n,
+                     "share": [round(float((d[m] < tau).double().mean()), 4) if n else None
+                               for tau in taus]}
+    return out
+
+
 def workload_quality(args, B, synth, Simulator):
     """Event quality against ESIM on the noise-free frames of the DVS clip
     (Sec. 3 "Quantitative comparison", Tables 1 and A2 on synthetic scenes),
@@ -312,10 +337,13 @@ def workload_quality(args, B, synth, Simulator):
             run = _graph(lambda s=sim, m=mode: s.enqueue(m))
             ms = _time_ms(run, 2)
             ev = sim.events()
-            m = Q.metrics(Q.to_device(ev), refd, W, H, T, taus, rmax)
+            evd = Q.to_device(ev)
+            m = Q.metrics(evd, refd, W, H, T, taus, rmax, keep=True)
             row[mode] = {"ms": round(ms, 3), "events": ev["count"],
                          "P": [round(v, 4) for v in m["P"]], "R": [round(v, 4) for v in m["R"]],
-                         "F": [round(v, 4) for v in m["F"]], "CD": m["CD"]}
+                         "F": [round(v, 4) for v in m["F"]], "CD": m["CD"],
+                         "precision_by_place": edge_split(spec, evd, m["dg"], cfg["r"], taus),
+                         "recall_by_place": edge_split(spec, refd, m["dr"], cfg["r"], taus)}
             del sim, run
             log(f"C={C} {mode}: {ms:.2f} ms, {ev['count']} events, F {row[mode]['F']}")
         rows.append(row)
@@ -581,6 +609,101 @@ def workload_multicrossing(args, B, synth, Simulator):
     return out
 
 
+KAPPA_DECADES = 13   # kappa-hat histogram bins: [10^k, 10^(k+1)) for k < 12, then >= 1e12
+
+
+def kappa_histogram(k):
+    """Counts of kappa-hat per decade (KAPPA_DECADES bins from 1) and of
+    non-finite values."""
+    fin = np.isfinite(k)
+    e = np.clip(np.floor(np.log10(np.maximum(k[fin], 1.0))), 0, KAPPA_DECADES - 1).astype(np.int64)
+    return np.bincount(e, minlength=KAPPA_DECADES), int((~fin).sum())
+
+
+def frame_log(sim, feat, params, emit):
+    """Per-frame record of one thresholded conversion, run untimed after the
+    timed steps: the flagged fraction and events of each frame, the number of
+    regressions re-solved in FP64 (compensated FP32 Gram only), a histogram of
+    the equilibrated condition estimate of the frame's regressions, and the
+    stuck pixels -- those whose stored gradient cannot reach the threshold for
+    any feature change within the clip's own feature range
+    (sum_j |beta_ref_j| span_j < C, so |dL| = |beta_ref^T (f - x_ref)| < C
+    forever).  emit(dict) receives one record per frame; the summary is
+    returned."""
+    import torch
+    from paper_2303_02608_amd import binding as B
+    p, n, T = sim.plan, sim.HW, sim.T
+    f32 = feat.float() if feat.dtype != torch.float32 else feat
+    span = torch.stack([(f32[:, j].amax() - f32[:, j].amin()) for j in range(sim.F)]).view(-1, 1)
+    del f32
+    kap = torch.empty(n, dtype=torch.float32, device=feat.device)
+    a2 = torch.empty(n, dtype=torch.float32, device=feat.device)
+    c32 = params.precision == B.GRAM_F32C
+    bound = params.kappa_fp64
+    hist_all = np.zeros(KAPPA_DECADES, np.int64)
+    nonfin_all = resolves_all = 0
+    phis, stucks = [], []
+
+    def stuck():
+        return int(((sim.state.beta.abs() * span).sum(0) < params.C).sum())
+
+    def kappas(t, wl, cnt, m):
+        B.regress(p, t, wl, cnt, n, a2, None, None, kap)
+        k = kap[:m].cpu().numpy().astype(np.float64)
+        h, nf = kappa_histogram(k)
+        res = int(np.sum(~(k <= bound))) if c32 else 0
+        return h, nf, res, float(np.max(k)) if k.size else 0.0
+
+    sim.ev.count.zero_()
+    B.regress(p, 0, None, None, n, sim.alpha, sim.beta)
+    B.events(p, 0, B.INIT, None, alpha=sim.alpha, beta=sim.beta, n_out=n)
+    h, nf, res, kmax = kappas(0, None, None, n)
+    hist_all += h
+    nonfin_all += nf
+    resolves_all += res
+    s = stuck()
+    stucks.append(s)
+    emit({"frame": 0, "regressions": n, "fp64_resolves": res, "kappa_hist": h.tolist(),
+          "kappa_nonfinite": nf, "kappa_max": kmax, "stuck": s})
+    ev_prev = 0
+    for t in range(1, T):
+        B.threshold(p, t, sim.dl, sim.worklist, sim.count)
+        B.regress(p, t, sim.worklist, sim.count, n, sim.alpha, sim.beta)
+        m = int(sim.count[1].item())
+        h, nf, res, kmax = kappas(t, sim.worklist, sim.count, m)
+        B.events(p, t, B.THRESHOLDED, sim.ev, worklist=sim.worklist, count=sim.count,
+                 dl=sim.dl, alpha=sim.alpha, beta=sim.beta, n_out=n)
+        ev = int(sim.ev.count[0].item())
+        s = stuck()
+        hist_all += h
+        nonfin_all += nf
+        resolves_all += res
+        phis.append(m / n)
+        stucks.append(s)
+        emit({"frame": t, "flagged": m, "phi": round(m / n, 6), "events": ev - ev_prev,
+              "fp64_resolves": res, "kappa_hist": h.tolist(), "kappa_nonfinite": nf,
+              "kappa_max": kmax, "stuck": s})
+        ev_prev = ev
+    return {"frames": T, "phi_min": round(min(phis), 6), "phi_median": round(float(np.median(phis)), 6),
+            "phi_max": round(max(phis), 6), "fp64_resolves": resolves_all,
+            "kappa_hist_decades_from_1": hist_all.tolist(), "kappa_nonfinite": nonfin_all,
+            "stuck_first_frame": stucks[0], "stuck_last_frame": stucks[-1], "stuck_max": max(stucks),
+            "precision": "compensated FP32 Gram" if c32 else "FP64 Gram (no re-solve)"}
+
+
+def cpu_model():
+    """The host CPU's model name (first processor of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
 def cpu_baseline(E, feat, r, tr, C, n_pixels):
     """The FP64 oracle, as it stands, on the host cores: the thresholded path
     over the whole clip for a random sample of pixels (their complete
@@ -602,7 +725,7 @@ def cpu_baseline(E, feat, r, tr, C, n_pixels):
     se = time.perf_counter() - c0
     log(f"oracle, exhaustive: {se:.1f}s for {pe.size} px x {T} frames")
     return {"value": round(pix.size * T / secs, 1), "unit": "pixel-frames/s", "cores": nthreads,
-            "kind": "oracle",
+            "cpu_model": cpu_model(), "kind": "oracle",
             "sample": f"{pix.size} random pixels x {T} frames of the same clip, thresholded "
                       f"path, FP64, {secs:.1f}s; events/s {out['count'] / secs:.1f}",
             "exhaustive": {"value": round(pe.size * T / se, 1), "unit": "pixel-frames/s",
@@ -632,6 +755,11 @@ def main():
                     help="dvs (default, the contract line) or one of the extension workloads")
     ap.add_argument("--precision-frames", type=int, default=None,
                     help="frames of the precision workload (default: all 500)")
+    ap.add_argument("--no-frame-log", action="store_true",
+                    help="skip the per-frame record (flagged fraction, events, FP64 re-solves, "
+                         "kappa-hat histogram, stuck pixels)")
+    ap.add_argument("--frame-log", type=str, default=None,
+                    help="write the per-frame JSON lines to this file (default: stderr)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 512 MiB read + 512 MiB write elementwise kernel (the "
                          "known-size reference for HBM counter calibration)")
@@ -683,7 +811,7 @@ def main():
         if args.save_clip:
             torch.save({"E": E.cpu(), "feat": feat.cpu()}, args.save_clip)
     y = torch.empty_like(E)
-    params = B.Params(r=r, tr=tr, C=C)
+    params = B.Params(r=r, tr=tr, C=C, dt=cfg["dt"])
     sim = Simulator(y, feat, params)
     pf = T * H * W
     B.log_brightness(E, out=y)
@@ -827,6 +955,22 @@ def main():
         exh["regress_tflops"] = round(regress_flops(om, F).sum() / (d2.sum() * 1e-3) / 1e12, 3)
         exh["regress_frac"] = round(exh["regress_tflops"] / PEAK_ALU_TFLOPS, 4)
 
+    # ---- per-frame record (untimed): phi, events, re-solves, kappa-hat, stuck
+    flog = None
+    if not args.no_frame_log:
+        fh = open(args.frame_log, "w") if args.frame_log else sys.stderr
+
+        def emit(rec):
+            print(json.dumps({"frame_log": rec}), file=fh, flush=True)
+
+        try:
+            flog = frame_log(sim, feat, params, emit)
+        finally:
+            if fh is not sys.stderr:
+                fh.close()
+        log(f"frame log: phi {flog['phi_min']}..{flog['phi_max']}, stuck pixels at the last "
+            f"frame {flog['stuck_last_frame']}, kappa-hat histogram {flog['kappa_hist_decades_from_1']}")
+
     # ---- CPU baseline: the FP64 oracle on a random pixel sample -----------
     cpu = None if args.no_cpu_baseline else cpu_baseline(E, feat, r, tr, C, args.cpu_pixels)
 
@@ -853,6 +997,7 @@ def main():
         "exhaustive": exh,
         "speedup_vs_exhaustive": round(exh["ms_per_step"] / ms_thr, 3) if exh else None,
         "roofline": roof,
+        "frame_log": flog,
         "cpu_baseline": cpu,
     }
     print(json.dumps(res), flush=True)

@@ -34,7 +34,12 @@ struct esim_plan_s {
   void* step_mem = nullptr;
   int64_t* xcd_bounds = nullptr;  // [5 lane counts][kMaxXcds + 1] dense group bounds per XCD (device)
   int64_t* step_wl = nullptr;     // [wl_capacity]
-  int32_t* step_count = nullptr;  // [2]
+  int32_t* step_count = nullptr;  // [4] (two segments of a split work list)
+  // esim_step's split work list: clips whose windows fit 16 columns (the
+  // one-pass list instance) in the first segment, wider ones from split_seg
+  // on (-1: one segment); the largest r of each segment
+  int64_t split_seg = -1;
+  int split_r[2] = {0, 0};
   float* step_alpha = nullptr;    // [npix]
   float* step_beta = nullptr;     // [F + 2][npix] (explicit thresholds only)
   int thr = ESIM_THRESHOLD_CLOSED;
@@ -81,7 +86,7 @@ namespace {
 
 int launch_plan_regress(esim_plan pl, int32_t t, const int64_t* worklist, const int32_t* count,
                         int64_t n_out, float* alpha, float* beta, float* resid, float* kappa,
-                        bool update_state, hipStream_t stream) {
+                        bool update_state, hipStream_t stream, int max_r = -1) {
   // the condition estimate of the FP64 Gram comes from a one-lane instance
   const bool kappa_f64 = kappa && pl->host[0].precision == ESIM_GRAM_F64;
   const int L = kappa_f64 ? 1 : worklist ? pl->lanes_list : pl->lanes_dense;
@@ -105,8 +110,8 @@ int launch_plan_regress(esim_plan pl, int32_t t, const int64_t* worklist, const 
   a.xcd_bounds = (!worklist && pl->nclips > 1) ? pl->xcd_bounds + (esim::kMaxXcds + 1) * esim::lanes_index(L)
                                                 : nullptr;
   a.nxcd = pl->shape.xcds;
-  int max_r = 0;
-  for (const auto& c : pl->host) max_r = std::max(max_r, static_cast<int>(c.r));
+  if (max_r < 0)
+    for (const auto& c : pl->host) max_r = std::max(max_r, static_cast<int>(c.r));
   return hip_check(esim::launch_regress(a, pl->F, pl->f16, pl->host[0].precision, L, pl->blocks_per_cu,
                                         max_r, pl->shape, stream),
                    "regress");
@@ -148,10 +153,10 @@ int store_moments(esim_plan pl, int32_t t, const int64_t* worklist, const int32_
 // Threshold at t into the plan's workspace, then the compaction (work list,
 // count and, with ev, the flagged pixels' events).
 int threshold_compact(esim_plan pl, int32_t t, float* dl, int64_t* worklist, int32_t* count,
-                      const esim::EventsDev* ev, hipStream_t s) {
+                      const esim::EventsDev* ev, hipStream_t s, int64_t seg_b = -1) {
   if (pl->thr == ESIM_THRESHOLD_CLOSED)
     return hip_check(esim::launch_flag_compact(pl->dev, pl->nclips, pl->nblk, t, esim::kFlagThreshold, dl,
-                                               nullptr, pl->ws, worklist, count, ev, s),
+                                               nullptr, pl->ws, worklist, count, ev, s, seg_b),
                      "threshold");
   int rc = explicit_ok(pl);
   if (rc != ESIM_OK) return rc;
@@ -322,6 +327,24 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     pl->npix = pix;
     pl->nblk = blk;
     pl->wl_capacity = wl;
+    {
+      // the split work list of esim_step (multi-clip plans with windows on
+      // both sides of 16 columns)
+      int64_t seg = 0;
+      bool narrow = false, wide = false;
+      for (auto& cd : pl->host) {
+        cd.list_class = 2 * cd.r + 1 > 16 ? 1 : 0;
+        if (cd.list_class) {
+          wide = true;
+          pl->split_r[1] = std::max(pl->split_r[1], static_cast<int>(cd.r));
+        } else {
+          narrow = true;
+          seg += cd.HW;
+          pl->split_r[0] = std::max(pl->split_r[0], static_cast<int>(cd.r));
+        }
+      }
+      pl->split_seg = narrow && wide ? seg : -1;
+    }
     for (int q = 0; q < 5; ++q) pl->dense_groups[q] = grp[q];
 
     // device memory: descriptors + workspace
@@ -331,7 +354,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     const size_t o_clips = off;
     off = align(off + clip_bytes);
     const size_t o_bcount = off;
-    off = align(off + sizeof(int32_t) * blk);
+    off = align(off + sizeof(int64_t) * blk);
     const size_t o_chunk = off;
     off = align(off + sizeof(int64_t) * ((blk + esim::kChunkBlocks - 1) / esim::kChunkBlocks));
     const size_t o_xcd = off;
@@ -349,7 +372,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
     }
     char* m = static_cast<char*>(pl->ws_mem);
     pl->dev = reinterpret_cast<esim::ClipDev*>(m + o_clips);
-    pl->ws.bcount = reinterpret_cast<int32_t*>(m + o_bcount);
+    pl->ws.bcount = reinterpret_cast<int64_t*>(m + o_bcount);
     pl->ws.chunk = reinterpret_cast<int64_t*>(m + o_chunk);
     pl->xcd_bounds = reinterpret_cast<int64_t*>(m + o_xcd);
     pl->ws.flags = reinterpret_cast<uint64_t*>(m + o_flags);
@@ -405,7 +428,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       const size_t s_wl = so;
       so = align(so + sizeof(int64_t) * std::max<int64_t>(wl, 1));
       const size_t s_cnt = so;
-      so = align(so + sizeof(int32_t) * 2);
+      so = align(so + sizeof(int32_t) * 4);
       const size_t s_al = so;
       so = align(so + sizeof(float) * pix);
       const size_t s_be = so;
@@ -574,8 +597,22 @@ int esim_step(esim_plan pl, int32_t t, int32_t mode, float* dl, esim_events_buf*
       return fail(ESIM_E_INVAL, "events buffer incomplete");
     esim::EventsDev ed{ev->x, ev->y, ev->t, ev->p, ev->clip, ev->capacity, ev->count, ev->ts};
     if (mode == ESIM_THRESHOLDED) {
-      int rc = threshold_compact(pl, t, dl, pl->step_wl, pl->step_count, &ed, s);
+      // Mixed window widths: the compaction writes the narrow clips' items and
+      // the wide ones' into two segments, and each gets its own launch, so the
+      // narrow ones run the one-pass list instance (one column per lane)
+      // instead of the general one, each launch spread over every XCD.
+      const bool split = pl->split_seg >= 0 && pl->thr == ESIM_THRESHOLD_CLOSED && pl->lanes_list == 16 &&
+                         pl->host[0].precision == ESIM_GRAM_F64;
+      int rc = threshold_compact(pl, t, dl, pl->step_wl, pl->step_count, &ed, s, split ? pl->split_seg : -1);
       if (rc != ESIM_OK) return rc;
+      if (split) {
+        rc = launch_plan_regress(pl, t, pl->step_wl, pl->step_count, pl->split_seg, nullptr, nullptr, nullptr,
+                                 nullptr, true, s, pl->split_r[0]);
+        if (rc != ESIM_OK) return rc;
+        return launch_plan_regress(pl, t, pl->step_wl + pl->split_seg, pl->step_count + 2,
+                                   pl->wl_capacity - pl->split_seg, nullptr, nullptr, nullptr, nullptr, true, s,
+                                   pl->split_r[1]);
+      }
       if (pl->thr == ESIM_THRESHOLD_CLOSED)
         return launch_plan_regress(pl, t, pl->step_wl, pl->step_count, pl->wl_capacity, nullptr, nullptr,
                                    nullptr, nullptr, true, s);

@@ -38,15 +38,20 @@ constexpr int64_t kDirectPrefixBlocks = 4096;
 // count (count[0] = count[1] = flagged pixels), and with ev also appends the
 // flagged pixels' events (the sign of the threshold's change); the other
 // modes append events to ev.
+// Split work list (kFlagThreshold, seg_b >= 0): the items of clips with
+// list_class 0 go to worklist[0, nA) and those of list_class 1 to
+// worklist[seg_b, seg_b + nB), each segment in ascending (clip, p) order;
+// count[0] = count[1] = nA, count[2] = count[3] = nB (count holds four).
+// The events keep their order, (clip, p) ascending over all clips.
 hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
                                float* dl, const float* alpha, const Workspace& ws, int64_t* worklist,
-                               int32_t* count, const EventsDev* ev, hipStream_t s);
+                               int32_t* count, const EventsDev* ev, hipStream_t s, int64_t seg_b = -1);
 
 // The compaction after a flag kernel that has already filled ws (chunk totals
-// when needed, then the scatter), as in launch_flag_compact.
+// when needed, then the scatter), as in launch_flag_compact (no split).
 hipError_t launch_scatter(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
                           const float* alpha, const Workspace& ws, int64_t* worklist, int32_t* count,
-                          const EventsDev* ev, hipStream_t s);
+                          const EventsDev* ev, hipStream_t s, int64_t seg_b = -1);
 
 // State <- the models of the work-list items (alpha[i], beta[.., i]), feat_t
 // and t, without events (the step's explicit-threshold path).

@@ -84,7 +84,7 @@ __device__ int block_exclusive_scan(int v) {
 
 __global__ void __launch_bounds__(kBlock)
 flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, float* __restrict__ dl,
-            const float* __restrict__ alpha, Workspace ws, const int64_t* __restrict__ ev_count) {
+            const float* __restrict__ alpha, Workspace ws, const int64_t* __restrict__ ev_count, int split) {
   __shared__ int wcount[kWavesPerBlock];
   const int64_t b = blockIdx.x;
   const int cl = block_clip(clips, nclips, b);
@@ -146,8 +146,11 @@ flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, floa
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int s = 0;
+    int64_t s = 0;
     for (int k = 0; k < kWavesPerBlock; ++k) s += wcount[k];
+    // a split compaction counts the second segment's items in the high half,
+    // so one prefix sum gives both ranks (the totals stay below 2^32)
+    if (split && C.list_class) s |= s << 32;
     ws.bcount[b] = s;
     // the event base of this step (the count is advanced by the scatter)
     if (b == 0) ws.misc[0] = ev_count ? *ev_count : 0;
@@ -190,15 +193,24 @@ __global__ void __launch_bounds__(kBlock) chunk_kernel(Workspace ws, int64_t nbl
 __global__ void __launch_bounds__(kBlock)
 scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, Workspace ws, int chunked,
                const float* __restrict__ alpha, int64_t* __restrict__ worklist, int32_t* __restrict__ count,
-               EventsDev ev) {
+               EventsDev ev, int64_t seg_b) {
+  constexpr int64_t kLow = 0xFFFFFFFFll;
   const int64_t b = blockIdx.x;
-  const int64_t off0 = counts_before(ws, b, chunked != 0);
+  const int64_t packed = counts_before(ws, b, chunked != 0);
+  const int64_t off0 = packed & kLow;         // flagged pixels before this block
+  const int64_t offb0 = packed >> 32;         // of them in second-segment clips (split only)
   const int64_t base = ws.misc[0];
   if (b == gridDim.x - 1 && threadIdx.x == 0) {
-    const int64_t total = off0 + ws.bcount[b];
+    const int64_t tp = packed + ws.bcount[b];
+    const int64_t total = tp & kLow;
     if (count) {
-      count[0] = static_cast<int32_t>(total);
-      count[1] = static_cast<int32_t>(total);
+      const int64_t nb = seg_b >= 0 ? tp >> 32 : 0;
+      count[0] = static_cast<int32_t>(total - nb);
+      count[1] = static_cast<int32_t>(total - nb);
+      if (seg_b >= 0) {
+        count[2] = static_cast<int32_t>(nb);
+        count[3] = static_cast<int32_t>(nb);
+      }
     }
     if (ev.count) *ev.count = base + total;
   }
@@ -245,10 +257,15 @@ scatter_kernel(const ClipDev* __restrict__ clips, int nclips, int t, int mode, W
   const uint64_t m = ws.flags[b * kWavesPerBlock + w];
   if (!((m >> lane) & 1ull)) return;
   const int64_t p = (b - C.blk_off) * kBlock + threadIdx.x;
-  int64_t off = off0;
-  for (int k = 0; k < w; ++k) off += __popcll(ws.flags[b * kWavesPerBlock + k]);
-  off += __popcll(m & ((1ull << lane) - 1ull));
-  if (mode == kFlagThreshold && worklist) worklist[off] = (static_cast<int64_t>(cl) << 32) | p;
+  int64_t rank = 0;                           // among the block's flagged pixels
+  for (int k = 0; k < w; ++k) rank += __popcll(ws.flags[b * kWavesPerBlock + k]);
+  rank += __popcll(m & ((1ull << lane) - 1ull));
+  const int64_t off = off0 + rank;
+  if (mode == kFlagThreshold && worklist) {
+    // a block lies in one clip, so its items all go to the same segment
+    const int64_t pos = seg_b < 0 ? off : C.list_class ? seg_b + offb0 + rank : off0 - offb0 + rank;
+    worklist[pos] = (static_cast<int64_t>(cl) << 32) | p;
+  }
   if (ev.x) {
     const int64_t e = base + off;
     if (e < ev.capacity) {
@@ -383,24 +400,26 @@ hipError_t launch_log(const float* E, float* y, int64_t n, float eps, hipStream_
 
 hipError_t launch_flag_compact(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
                                float* dl, const float* alpha, const Workspace& ws, int64_t* worklist,
-                               int32_t* count, const EventsDev* ev, hipStream_t s) {
+                               int32_t* count, const EventsDev* ev, hipStream_t s, int64_t seg_b) {
   int64_t* wl = mode == kFlagThreshold ? worklist : nullptr;
+  if (!wl) seg_b = -1;
   hipLaunchKernelGGL(flag_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
-                     t, mode, dl, alpha, ws, ev ? ev->count : nullptr);
-  return launch_scatter(clips, nclips, nblk, t, mode, alpha, ws, wl, count, ev, s);
+                     t, mode, dl, alpha, ws, ev ? ev->count : nullptr, seg_b >= 0 ? 1 : 0);
+  return launch_scatter(clips, nclips, nblk, t, mode, alpha, ws, wl, count, ev, s, seg_b);
 }
 
 hipError_t launch_scatter(const ClipDev* clips, int nclips, int64_t nblk, int t, int mode,
                           const float* alpha, const Workspace& ws, int64_t* worklist, int32_t* count,
-                          const EventsDev* ev, hipStream_t s) {
+                          const EventsDev* ev, hipStream_t s, int64_t seg_b) {
   int64_t* wl = mode == kFlagThreshold ? worklist : nullptr;
+  if (!wl) seg_b = -1;
   const int chunked = nblk > kDirectPrefixBlocks ? 1 : 0;
   if (chunked)
     hipLaunchKernelGGL(chunk_kernel, dim3(static_cast<unsigned>((nblk + kChunkBlocks - 1) / kChunkBlocks)),
                        dim3(kBlock), 0, s, ws, nblk);
   EventsDev none{};
   hipLaunchKernelGGL(scatter_kernel, dim3(static_cast<unsigned>(nblk)), dim3(kBlock), 0, s, clips, nclips,
-                     t, mode, ws, chunked, alpha, wl, wl ? count : nullptr, ev ? *ev : none);
+                     t, mode, ws, chunked, alpha, wl, wl ? count : nullptr, ev ? *ev : none, seg_b);
   return hipGetLastError();
 }
 

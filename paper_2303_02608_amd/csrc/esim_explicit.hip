@@ -260,7 +260,7 @@ explicit_flag_kernel(const ClipDev* __restrict__ clips, int nclips, int t, float
   }
   __syncthreads();
   if (threadIdx.x == 0) {
-    int s = 0;
+    int64_t s = 0;
     for (int k = 0; k < kWavesPerBlock; ++k) s += wcount[k];
     ws.bcount[b] = s;
     if (b == 0) ws.misc[0] = ev_count ? *ev_count : 0;

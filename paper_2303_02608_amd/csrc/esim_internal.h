@@ -39,6 +39,8 @@ struct ClipDev {
   float* st_rmom;          // [2][HW] R and mean residual of the stored plane (nullable)
   int32_t thr;             // esim_threshold
   double dt;               // time between frames (event times t * dt)
+  int32_t list_class;      // 1: esim_step's split work list puts this clip's items in its second
+                           // segment (windows wider than 16 columns), 0 otherwise
 };
 
 // Shape of the device a plan runs on, queried once when the plan is created:
@@ -55,7 +57,8 @@ bool query_device_shape(DeviceShape& out);
 
 // Compaction workspace of a plan (device).
 struct Workspace {
-  int32_t* bcount;         // [nblk] flagged pixels per block
+  int64_t* bcount;         // [nblk] flagged pixels per block; a split compaction also adds the
+                           // count times 2^32 for blocks of second-segment clips
   uint64_t* flags;         // [nblk][kWavesPerBlock] flag ballots
   uint64_t* pol;           // [nblk][kWavesPerBlock] positive-polarity ballots
   int64_t* misc;           // [4] [0] event base of the current step

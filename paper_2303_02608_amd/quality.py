@@ -31,7 +31,9 @@ def to_device(ev: Dict[str, np.ndarray], device="cuda") -> Dict[str, torch.Tenso
 
 
 def metrics(gen: Dict[str, torch.Tensor], ref: Dict[str, torch.Tensor], W: int, H: int, T: int,
-            taus: Iterable[float], rmax: float) -> Dict[str, object]:
+            taus: Iterable[float], rmax: float, keep: bool = False) -> Dict[str, object]:
+    """P, R, F per tau and CD; with ``keep`` also the per-event distances
+    ``dg`` (generated -> reference) and ``dr`` (reference -> generated)."""
     dg = B.nn_distances(ref, gen, W, H, T, rmax)     # generated -> reference
     dr = B.nn_distances(gen, ref, W, H, T, rmax)     # reference -> generated
     out = {"P": [], "R": [], "F": []}
@@ -44,4 +46,6 @@ def metrics(gen: Dict[str, torch.Tensor], ref: Dict[str, torch.Tensor], W: int, 
     cg = torch.clamp(dg, max=rmax) ** 2
     cr = torch.clamp(dr, max=rmax) ** 2
     out["CD"] = float((cg.mean() if cg.numel() else 0.0) + (cr.mean() if cr.numel() else 0.0))
+    if keep:
+        out["dg"], out["dr"] = dg, dr
     return out

@@ -456,6 +456,25 @@ def make_clip(spec: ClipSpec, device="cpu", frames: Optional[Sequence[int]] = No
     return out
 
 
+def boundary_distance(spec: ClipSpec, t: torch.Tensor, x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
+    """Distance in pixels from the centres of pixels (x, y) at frames t (int
+    tensors of one shape) to the nearest disc outline of the scene at that
+    frame (inf for a scene without discs): the ground truth of where surfaces
+    meet, for splitting events into those at moving edges and the rest."""
+    dev = t.device
+    scene = _Scene(spec, dev)
+    px = x.to(torch.float64) + 0.5
+    py = y.to(torch.float64) + 0.5
+    best = torch.full(t.shape, float("inf"), dtype=torch.float64, device=dev)
+    tf = torch.arange(spec.T, dtype=torch.float64, device=dev)
+    ti = t.to(torch.int64)
+    for k, d in enumerate(scene.discs):
+        cx, cy, _, _, _ = scene.disc_states(k, tf)
+        dist = torch.abs(torch.hypot(px - cx[ti], py - cy[ti]) - d["R"])
+        best = torch.minimum(best, dist)
+    return best
+
+
 def random_features_clip(W: int, H: int, T: int, F: int, seed: int, device="cpu",
                          feat_dtype: str = "f32", scale: float = 0.5):
     """Unstructured clip: i.i.d. uniform features in [-scale, scale] and

@@ -63,7 +63,8 @@ def test_batch_equals_single_clips_and_oracle():
 
 
 def test_batch_graph_replay():
-    clips = _clips()[:3]
+    # radii 3, 2 and 9: the step's work list is split in two segments
+    clips = [_clips()[k] for k in (0, 1, 5)]
     say("batch graph replay")
     devs = [to_dev(E, f) for E, f, _ in clips]
     bs = BatchSimulator([y for y, _ in devs], [f for _, f in devs], [p for *_, p in clips])
@@ -75,3 +76,36 @@ def test_batch_graph_replay():
         got = bs.ev.host()
         for k in ("x", "y", "t", "p", "clip"):
             assert np.array_equal(got[k], eager[k])
+
+
+@pytest.mark.parametrize("radii", [(5, 8), (8, 5, 6)])
+def test_split_work_list_with_chunked_prefix(radii):
+    """Plans of more than 4096 flag blocks (the prefix goes through chunk
+    totals) with windows on both sides of 16 columns: the step's two list
+    segments give the events of each clip converted alone, bit for bit, in
+    (t, clip, py, px) order."""
+    say(f"split work list, chunked prefix, radii {radii}")
+    ys, fs, ps = [], [], []
+    for i, r in enumerate(radii):
+        spec = synth.ClipSpec(W=1024, H=600, T=4, spp=2, F=7, n_discs=12, speed=(1.0, 3.0),
+                              seed=5100 + i)
+        d = synth.make_clip(spec, device="cuda")
+        ys.append(B.log_brightness(d["E"]))
+        fs.append(d["feat"])
+        ps.append(B.Params(r=r, tr=1, C=0.2))
+    bs = BatchSimulator(ys, fs, ps)
+    assert bs.plan.npix // 256 > 4096
+    got = bs.run()
+    assert got["count"] > 0
+    sep = bs.run(fused=False)
+    for k in ("x", "y", "t", "p", "clip"):
+        assert np.array_equal(got[k], sep[k]), k
+    for c, (y, f, p) in enumerate(zip(ys, fs, ps)):
+        m = got["clip"] == c
+        single = Simulator(y, f, p).run("thresholded")
+        assert m.sum() > 0
+        assert _key(got["x"][m], got["y"][m], got["t"][m], got["p"][m]) == \
+            _key(single["x"], single["y"], single["t"], single["p"]), c
+    k = (got["t"].astype(np.int64) << 40) + (got["clip"].astype(np.int64) << 28) + \
+        got["y"].astype(np.int64) * 4096 + got["x"]
+    assert np.all(np.diff(k) > 0)
