@@ -712,7 +712,7 @@ int esim_wlr_backward(esim_plan pl, const int64_t* items, int64_t n, const float
     if (!items || !g_alpha || !g_y || !g_b) return fail(ESIM_E_INVAL, "null argument");
     if (pl->max_feat_bytes >= (1ull << 32) || pl->max_y_bytes >= (1ull << 32))
       return fail(ESIM_E_UNSUPPORTED, "backward needs feature and brightness arrays below 4 GiB");
-    if (esim::backward_gather_lds_bytes(pl->host[0]) > esim::kMaxGatherLds)
+    if (pl->host[0].r > 25 || esim::backward_gather_lds_bytes(pl->host[0]) > esim::kMaxGatherLds)
       return fail(ESIM_E_UNSUPPORTED, "backward supports window radii up to 25");
     const size_t need = esim::backward_scratch_bytes(pl->host[0], n);
     if (!scratch || scratch_bytes < need) return fail(ESIM_E_CAPACITY, "scratch too small");

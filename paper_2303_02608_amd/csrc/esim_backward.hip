@@ -10,15 +10,19 @@
 //
 // Kernels, all deterministic (no atomics on values):
 //   fill_map / map_items  a dense (frame, pixel) -> item index map
-//   adjoint_kernel        per item: recompute the window, Gram, Cholesky,
-//                         theta and v (the window is not stored by the forward
-//                         pass); a second window pass writes each sample's
-//                         contribution g_alpha (w_i / W) s_i to the item's slot
-//                         and sums the bandwidth gradient over the item's lanes
-//   gather_kernel         per input (frame, pixel): sums, in a fixed order, the
-//                         contributions of every item whose window holds it
-//                         (item rows staged in LDS per tile of an input row)
-//   reduce_gb_*           fixed-order two-level sum of the per-item b gradients
+//   adjoint_kernel        per item: the window's Gram, Cholesky, theta and v
+//                         (the window is recomputed, not stored by the forward
+//                         pass); writes the item's record c = g_alpha v / W,
+//                         theta, q = g_alpha v^T Lambda theta / W
+//   gather_kernel         per input sample (frame, pixel): for every item whose
+//                         window holds it, in a fixed order, recomputes the
+//                         sample's weight and regressors from the item's
+//                         centre features and record, adds w_i c^T z_i to g_y
+//                         and accumulates w_i (c^T z_i r_i - q) z_ij^2 for the
+//                         bandwidths.  A wave owns 8 x 8 samples and walks the
+//                         items staged in LDS one at a time, every lane reading
+//                         the same record (a broadcast); per-block partials
+//   reduce_gb_*           fixed-order two-level sum of the per-block partials
 #include "esim_wlr.h"
 
 namespace esim {
@@ -27,14 +31,17 @@ namespace {
 constexpr int kAdjLanes = 4;        // lanes per item, windows wider than 16 columns
 constexpr int kAdjLanesWide = 16;   // lanes per item, windows of at most 16 columns
 constexpr int kRedBlocks = 256;
+constexpr int kGatherTile = 16;     // input pixels of a gather block: 16 x 16, four waves of 8 x 8
+constexpr int kGatherThreads = 256;
+constexpr size_t kGatherLdsBudget = 36864;
 
 struct BwdDev {
   int32_t* item_map;   // [T*HW]
-  float* contrib;      // [n][S]
-  double* gbpart;      // [n][D]
+  double* rec;         // [n][2P + 1] per-item records (c, theta, q)
+  double* gbpart;      // [npart][D] per-gather-block bandwidth partials
   double* gbblk;       // [kRedBlocks][D]
-  int64_t S;           // window slots per item: (2r+1)^2 (2tr+1)
   int64_t n;
+  int64_t npart;
 };
 
 __global__ void __launch_bounds__(256) fill_map_kernel(int32_t* m, int64_t n) {
@@ -62,20 +69,18 @@ map_items_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ 
   }
 }
 
-template <int F, int L, bool F16>
+template <int F, int L, bool F16, bool ONE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(F <= 8 ? 2 : 1)))
 adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ items,
                const float* __restrict__ g_alpha, BwdDev bd, int nxcd) {
-  constexpr int D = F + 2;
   constexpr int P = F + 3;
+  constexpr int R = 2 * P + 1;
   constexpr int G = kWave / L;
   const ClipDev& C = clips[0];
   const int lane = threadIdx.x & (kWave - 1);
   const int slot = lane / L;
   const int j = lane % L;
   const int64_t ngroups = (bd.n + G - 1) / G;
-  const int r = C.r, tr = C.tr;
-  const int span = 2 * r + 1;
   GroupIter it_groups(ngroups, nxcd);
   int64_t g;
   while (it_groups.next(g)) {
@@ -83,22 +88,23 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
     int64_t pix = 0;
     int t = 0;
     const bool active = i < bd.n && item_ok(C, items[i], g_alpha, i, pix, t);
-    if (__ballot(active) == 0) {
-      if (i < bd.n && j == 0)
-        for (int d = 0; d < D; ++d) bd.gbpart[i * D + d] = 0.0;
-      continue;
-    }
+    if (__ballot(active) == 0) continue;
     ItemGeom<F, F16, double> geo;
     make_geom(geo, C, active ? pix : 0, active ? t : 0, 0, C.T, active);
 
     Gram<F, double> gm;
-    gm.zero_snap();
-    window_loop<F, L, F16, double>(
-        geo, j, [&](double) { gm.pass_begin_snap(); },
-        [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
-          gm.add_onepass(w, yd, v, vy);
-        },
-        [&](double vx) { gm.pass_end_snap(vx); });
+    auto add = [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
+      gm.add_onepass(w, yd, v, vy);
+    };
+    if constexpr (ONE) {
+      // every lane owns one column of the window (2r + 1 <= L, checked by the launcher)
+      gm.zero_onepass();
+      window_loop<F, L, F16, double>(geo, j, [&](double) {}, add, [&](double vx) { gm.fold_onepass(vx); });
+    } else {
+      gm.zero_snap();
+      window_loop<F, L, F16, double>(geo, j, [&](double) { gm.pass_begin_snap(); }, add,
+                                     [&](double vx) { gm.pass_end_snap(vx); });
+    }
     gm.template lane_sum<L>();
     double M[P * (P + 1) / 2], rhs[P], th[P], anorm;
     const double iW = gram_solve<F, double>(gm, C, M, rhs, th, anorm);
@@ -109,146 +115,191 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
     double vLt = 0.0;      // v^T Lambda theta (Lambda = scaled ridge on the beta block)
 #pragma unroll
     for (int k = 1; k < P; ++k) vLt = fma(vv[k] * (C.ridge * C.c2[k - 1]), th[k], vLt);
-    const double ga = active ? static_cast<double>(g_alpha[i]) : 0.0;
-    float* ci = bd.contrib + (active ? i : 0) * bd.S;
-
-    double gb[D];
+    if (active && j == 0) {
+      const double gw = static_cast<double>(g_alpha[i]) * iW;
+      double* o = bd.rec + i * R;
 #pragma unroll
-    for (int d = 0; d < D; ++d) gb[d] = 0.0;
-    double cur_vx = 0.0;
-    window_loop<F, L, F16, double>(
-        geo, j, [&](double vx) { cur_vx = vx; },
-        [&](double w, double yd, const double (&v)[F], double vy, int dx, int dt, int dy, bool ok) {
-          double s = fma(vv[1], cur_vx, fma(vv[2], vy, vv[0]));
-          double pred = fma(th[1], cur_vx, fma(th[2], vy, th[0]));
-#pragma unroll
-          for (int f = 0; f < F; ++f) {
-            s = fma(vv[3 + f], v[f], s);
-            pred = fma(th[3 + f], v[f], pred);
-          }
-          const double res = yd - pred;
-          // only in-image samples have a slot the gather reads
-          if (ok) ci[((dt + tr) * span + (dy + r)) * span + (dx + r)] = static_cast<float>(ga * w * iW * s);
-          const double k = ga * (s * res - vLt) * iW * w;
-          gb[0] = fma(k, cur_vx * cur_vx, gb[0]);
-          gb[1] = fma(k, vy * vy, gb[1]);
-#pragma unroll
-          for (int f = 0; f < F; ++f) gb[2 + f] = fma(k, v[f] * v[f], gb[2 + f]);
-        },
-        [&](double) {});
-#pragma unroll
-    for (int d = 0; d < D; ++d) gb[d] = group_sum<L>(gb[d]);
-    if (i < bd.n && j == 0) {
-#pragma unroll
-      for (int d = 0; d < D; ++d)
-        bd.gbpart[i * D + d] = active ? gb[d] * C.sf[d] * C.h : 0.0;   // / b_d = * sf_d * h
+      for (int k = 0; k < P; ++k) {
+        o[k] = gw * vv[k];
+        o[P + k] = th[k];
+      }
+      o[2 * P] = gw * vLt;
     }
   }
 }
 
-// One block per (frame, row, tile of kGatherTile columns) of inputs.  For each
-// item row (tc, yc) that can reach the tile, in ascending order, the block
-// stages the map row and the items' contributions to this input row (2r + 1
-// consecutive slots per item, coalesced) in LDS; each thread then adds, for
-// its input column, the items at xc = xq - r .. xq + r in ascending order.
-// The order of the sum (tc, yc, xc ascending) is fixed, so the result does not
-// depend on scheduling.
-constexpr int kGatherTile = 256;
+// LDS bytes of one staged item row of the gather (map, record and centre
+// features for each column the block's tile and the window reach, and the
+// row's presence mask).
+size_t gather_row_bytes(int F, int r) {
+  const int P = F + 3;
+  return static_cast<size_t>(kGatherTile + 2 * r) *
+             (sizeof(int32_t) + sizeof(double) * (2 * P + 1) + sizeof(double) * F) +
+         2 * sizeof(uint64_t);
+}
 
-__global__ void __launch_bounds__(kGatherTile)
-gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ g_y) {
-  extern __shared__ float sm[];
+// Item rows staged per band (within the LDS budget, at least one).
+int gather_band_rows(int F, int r) {
+  return std::max(1, static_cast<int>(kGatherLdsBudget / gather_row_bytes(F, r)));
+}
+
+// One block per (input frame tq, 16 x 16 tile of input pixels); wave w owns the
+// 8 x 8 sub-tile (w & 1, w >> 1), lane l the sample (l & 7, l >> 3) in it.  The
+// item rows (yc, tc) that reach the tile are taken in a fixed order (yc
+// ascending, then tc), nbr rows per band: the block stages the band's items
+// (records, centre features, presence masks) for the columns the tile's
+// windows reach, then each wave walks the band's present items in order (rows,
+// then columns ascending), skipping those outside all of its lanes' windows,
+// and every lane whose window holds the item adds its sample's terms.  The
+// order of every sum is fixed, so g_y and the partials do not depend on
+// scheduling.
+template <int F>
+__global__ void __launch_bounds__(kGatherThreads)
+gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ g_y, int nbr) {
+  constexpr int D = F + 2;
+  constexpr int P = F + 3;
+  constexpr int R = 2 * P + 1;
+  constexpr double K = kHalfLog2e;
+  extern __shared__ double sm[];
   const ClipDev& C = clips[0];
   const int r = C.r, tr = C.tr, W = C.W, H = C.H, T = C.T;
-  const int span = 2 * r + 1;
-  const int seg = kGatherTile + 2 * r;                 // staged columns
-  int32_t* mrow = reinterpret_cast<int32_t*>(sm);      // [seg]
-  float* cx = sm + seg;                                // [seg][span]
-  const int ntile = (W + kGatherTile - 1) / kGatherTile;
-  const int64_t b = blockIdx.x;
-  const int tile = static_cast<int>(b % ntile);
-  const int64_t rowq = b / ntile;                      // tq * H + yq
-  const int tq = static_cast<int>(rowq / H), yq = static_cast<int>(rowq % H);
-  const int x_lo = tile * kGatherTile;
-  const int xs = x_lo - r;                             // column of staged index 0
-  const int xq = x_lo + static_cast<int>(threadIdx.x);
+  const int ncol = kGatherTile + 2 * r;                        // at most 128 (r <= 56)
+  double* srec = sm;                                            // [nbr][ncol][R]
+  double* sxcs = srec + static_cast<size_t>(nbr) * ncol * R;    // [nbr][ncol][F]
+  uint64_t* smask = reinterpret_cast<uint64_t*>(sxcs + static_cast<size_t>(nbr) * ncol * F);  // [nbr][2]
+  int32_t* smap = reinterpret_cast<int32_t*>(smask + 2 * nbr);  // [nbr][ncol]
+  const int ntx = (W + kGatherTile - 1) / kGatherTile;
+  const int nty = (H + kGatherTile - 1) / kGatherTile;
+  int64_t b = blockIdx.x;
+  const int tx = static_cast<int>(b % ntx);
+  b /= ntx;
+  const int ty = static_cast<int>(b % nty);
+  const int tq = static_cast<int>(b / nty);
+  const int bx0 = tx * kGatherTile, by0 = ty * kGatherTile;
   const int lane = static_cast<int>(threadIdx.x) & (kWave - 1);
-  const int wave = static_cast<int>(threadIdx.x) / kWave;
+  const int wv = static_cast<int>(threadIdx.x) / kWave;
+  const int wx0 = bx0 + 8 * (wv & 1), wy0 = by0 + 8 * (wv >> 1);
+  const int xq = wx0 + (lane & 7), yq = wy0 + (lane >> 3);
+  const bool in = xq < W && yq < H;
+  const int xs = bx0 - r;                      // image column of staged column 0
+  // staged columns whose items reach the wave's columns: wx0 - r .. wx0 + 7 + r
+  const int wc0 = wx0 - r - xs;
+  const int64_t pq = in ? static_cast<int64_t>(yq) * W + xq : 0;
+  double fi[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) fi[f] = in ? static_cast<double>(feat_value(C, tq, f, pq)) : 0.0;
+  const double yi = in ? static_cast<double>(C.y[static_cast<int64_t>(tq) * C.HW + pq]) : 0.0;
+  double sf[F];
+#pragma unroll
+  for (int f = 0; f < F; ++f) sf[f] = C.sf[2 + f];
+  const double vx_step = C.sf[0] / r, vy_step = C.sf[1] / r;
   double acc = 0.0;
+  double gb[D];
+#pragma unroll
+  for (int d = 0; d < D; ++d) gb[d] = 0.0;
   const int t0 = max(0, tq - tr), t1 = min(T - 1, tq + tr);
-  const int y0 = max(0, yq - r), y1 = min(H - 1, yq + r);
-  // item rows (tc, yc) in ascending order, k = (tc - t0) * ny + (yc - y0); the
-  // map entries of row k + 1 are loaded into registers while row k is used
-  const int ny = y1 - y0 + 1;
-  const int nrow = (t1 - t0 + 1) * ny;
-  constexpr int kPer = 2;                              // staged columns per thread (seg <= 2 tile)
-  auto load_map = [&](int k, int32_t (&v)[kPer]) {
-    const int tc = t0 + k / ny, yc = y0 + k % ny;
-    const int32_t* row = bd.item_map + static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W;
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int c = static_cast<int>(threadIdx.x) + q * kGatherTile;
+  const int ntc = t1 - t0 + 1;
+  const int yc0 = max(0, by0 - r), yc1 = min(H - 1, by0 + kGatherTile - 1 + r);
+  const int nrow = (yc1 - yc0 + 1) * ntc;      // item rows, k = (yc - yc0) * ntc + (tc - t0)
+  for (int k0 = 0; k0 < nrow; k0 += nbr) {
+    const int nbk = min(nbr, nrow - k0);
+    __syncthreads();                           // the previous band's reads are done
+    if (threadIdx.x < 2 * nbk) smask[threadIdx.x] = 0;
+    __syncthreads();
+    for (int q = static_cast<int>(threadIdx.x); q < nbk * ncol; q += kGatherThreads) {
+      const int kk = q / ncol, c = q - kk * ncol;
+      const int k = k0 + kk;
+      const int yc = yc0 + k / ntc, tc = t0 + k % ntc;
       const int x = xs + c;
-      v[q] = (c < seg && x >= 0 && x < W) ? row[x] : -1;
-    }
-  };
-  int32_t nxt[kPer];
-  if (nrow > 0) load_map(0, nxt);
-  for (int k = 0; k < nrow; ++k) {
-    const int tc = t0 + k / ny, yc = y0 + k % ny;
+      int32_t it = -1;
+      if (x >= 0 && x < W) it = bd.item_map[static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W + x];
+      smap[q] = it;
+      if (it >= 0) {
+        atomicOr(reinterpret_cast<unsigned long long*>(&smask[2 * kk + (c >> 6)]), 1ull << (c & 63));
+        const double* src = bd.rec + static_cast<int64_t>(it) * R;
 #pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int c = static_cast<int>(threadIdx.x) + q * kGatherTile;
-      if (c < seg) mrow[c] = nxt[q];
+        for (int e = 0; e < R; ++e) srec[static_cast<size_t>(q) * R + e] = src[e];
+        const int64_t p = static_cast<int64_t>(yc) * W + x;
+#pragma unroll
+        for (int f = 0; f < F; ++f)
+          sxcs[static_cast<size_t>(q) * F + f] = static_cast<double>(feat_value(C, tc, f, p)) * sf[f];
+      }
     }
     __syncthreads();
-    if (k + 1 < nrow) load_map(k + 1, nxt);
-    // each wave walks the present items of its 64-column chunks (a
-    // wave-uniform loop over the ballot); the lanes load the items' slots,
-    // coalesced 4 (2r + 1)-byte reads: four items per step for windows of at
-    // most 16 columns, one otherwise
-    const int64_t sbase = static_cast<int64_t>((tq - tc + tr) * span + (yq - yc + r)) * span;
-    for (int base = wave * kWave; base < seg; base += kGatherTile) {
-      const int c = base + lane;
-      const int32_t it = c < seg ? mrow[c] : -1;
-      uint64_t mask = __ballot(it >= 0);
-      if (span <= 16) {
-        // four items per step, 16 lanes each (lane q * 16 + m takes slot m of
-        // the q-th next item)
-        const int q = lane >> 4, m = lane & 15;
-        while (mask != 0) {
-          int bits[4];
+    for (int kk = 0; kk < nbk; ++kk) {
+      const int k = k0 + kk;
+      const int yc = yc0 + k / ntc;
+      // rows out of reach of every lane of the wave (wave-uniform)
+      if (yc < wy0 - r || yc > wy0 + 7 + r) continue;
+      const int dy = yq - yc;
+      const bool row_ok = in && dy >= -r && dy <= r;
+      const double vy = static_cast<double>(dy) * vy_step;
+      const double kyy = K * vy;
+      for (int word = 0; word < 2; ++word) {
+        // the same mask for every lane: kept in scalar registers
+        const uint64_t mv = smask[2 * kk + word];
+        uint64_t m = static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(mv)))) |
+                     (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(mv >> 32))))
+                      << 32);
+        // the wave's columns wc0 .. wc0 + 7 + 2r of the staged row
+        const int lo = wc0 - 64 * word, hi = wc0 + 7 + 2 * r - 64 * word;
+        if (hi < 0 || lo > 63) continue;
+        if (lo > 0) m &= ~0ull << lo;
+        if (hi < 63) m &= ~0ull >> (63 - hi);
+        while (m != 0) {
+          const int c = __ffsll(static_cast<unsigned long long>(m)) - 1 + 64 * word;
+          m &= m - 1;
+          const int dx = xq - (xs + c);
+          if (!row_ok || dx < -r || dx > r) continue;
+          const int q = kk * ncol + c;
+          const double* rc = srec + static_cast<size_t>(q) * R;
+          const double* xc = sxcs + static_cast<size_t>(q) * F;
+          // the sample's regressors and weight as the item's window pass forms them
+          const double vx = static_cast<double>(dx) * vx_step;
+          double v[F];
+          double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-          for (int u = 0; u < 4; ++u) {
-            bits[u] = mask != 0 ? __ffsll(static_cast<unsigned long long>(mask)) - 1 : -1;
-            if (mask != 0) mask &= mask - 1;
+          for (int f = 0; f < F; ++f) {
+            v[f] = fma(fi[f], sf[f], -xc[f]);
+            if (f & 1) s1 = fma(v[f], v[f], s1);
+            else s0 = fma(v[f], v[f], s0);
           }
-          const int bq = q == 0 ? bits[0] : q == 1 ? bits[1] : q == 2 ? bits[2] : bits[3];
-          const int32_t itc = __shfl(it, bq < 0 ? 0 : bq);
-          if (bq >= 0 && m < span)
-            cx[(base + bq) * span + m] = bd.contrib[static_cast<int64_t>(itc) * bd.S + sbase + m];
-        }
-      } else {
-        while (mask != 0) {
-          const int bit = __ffsll(static_cast<unsigned long long>(mask)) - 1;
-          mask &= mask - 1;
-          const int32_t itc = __shfl(it, bit);
-          for (int mm = lane; mm < span; mm += kWave)
-            cx[(base + bit) * span + mm] = bd.contrib[static_cast<int64_t>(itc) * bd.S + sbase + mm];
+          const double arg = fma(s0 + s1, K, fma(kyy, vy, K * vx * vx));
+          const double w = static_cast<double>(__builtin_amdgcn_exp2f(static_cast<float>(arg)));
+          double cs = fma(rc[1], vx, fma(rc[2], vy, rc[0]));
+          double pred = fma(rc[P + 1], vx, fma(rc[P + 2], vy, rc[P]));
+#pragma unroll
+          for (int f = 0; f < F; ++f) {
+            cs = fma(rc[3 + f], v[f], cs);
+            pred = fma(rc[P + 3 + f], v[f], pred);
+          }
+          acc = fma(w, cs, acc);
+          const double kq = w * fma(cs, yi - pred, -rc[2 * P]);
+          gb[0] = fma(kq, vx * vx, gb[0]);
+          gb[1] = fma(kq, vy * vy, gb[1]);
+#pragma unroll
+          for (int f = 0; f < F; ++f) gb[2 + f] = fma(kq, v[f] * v[f], gb[2 + f]);
         }
       }
     }
-    __syncthreads();
-    if (xq < W) {
-      // items at xc = xq - r + m (staged index threadIdx.x + m), slot x-index span - 1 - m
-      for (int m = 0; m < span; ++m) {
-        const int c = static_cast<int>(threadIdx.x) + m;
-        if (mrow[c] >= 0) acc += static_cast<double>(cx[c * span + (span - 1 - m)]);
-      }
-    }
-    __syncthreads();
   }
-  if (xq < W && acc != 0.0) g_y[rowq * W + xq] += static_cast<float>(acc);
+  if (in && acc != 0.0) g_y[static_cast<int64_t>(tq) * C.HW + pq] += static_cast<float>(acc);
+  // bandwidth partials of the block: a fixed butterfly inside each wave, then
+  // the waves in order
+#pragma unroll
+  for (int d = 0; d < D; ++d)
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) gb[d] += __shfl_xor(gb[d], o);
+  __syncthreads();                             // the last band's reads are done
+  if (lane == 0)
+#pragma unroll
+    for (int d = 0; d < D; ++d) sm[wv * D + d] = gb[d];
+  __syncthreads();
+  if (threadIdx.x < D) {
+    double s = 0.0;
+    for (int w2 = 0; w2 < kGatherThreads / kWave; ++w2) s += sm[w2 * D + threadIdx.x];
+    bd.gbpart[static_cast<int64_t>(blockIdx.x) * D + threadIdx.x] = s * C.sf[threadIdx.x] * C.h;
+  }
 }
 
 template <int D>
@@ -257,7 +308,7 @@ __global__ void __launch_bounds__(256) reduce_gb_blocks(BwdDev bd) {
   double acc[D];
 #pragma unroll
   for (int d = 0; d < D; ++d) acc[d] = 0.0;
-  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < bd.n;
+  for (int64_t i = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x; i < bd.npart;
        i += static_cast<int64_t>(gridDim.x) * 256)
 #pragma unroll
     for (int d = 0; d < D; ++d) acc[d] += bd.gbpart[i * D + d];
@@ -282,11 +333,13 @@ __global__ void reduce_gb_final(BwdDev bd, int nblk, int D, double* g_b) {
 }
 
 using AdjFn = void (*)(const ClipDev*, const int64_t*, const float*, BwdDev, int);
+using GatherFn = void (*)(const ClipDev*, BwdDev, float*, int);
 
 template <int F>
 AdjFn pick_adj(bool f16, bool wide) {
-  if (wide) return f16 ? adjoint_kernel<F, kAdjLanesWide, true> : adjoint_kernel<F, kAdjLanesWide, false>;
-  return f16 ? adjoint_kernel<F, kAdjLanes, true> : adjoint_kernel<F, kAdjLanes, false>;
+  if (wide)
+    return f16 ? adjoint_kernel<F, kAdjLanesWide, true, true> : adjoint_kernel<F, kAdjLanesWide, false, true>;
+  return f16 ? adjoint_kernel<F, kAdjLanes, true, false> : adjoint_kernel<F, kAdjLanes, false, false>;
 }
 
 AdjFn pick(int F, bool f16, bool wide) {
@@ -303,6 +356,24 @@ AdjFn pick(int F, bool f16, bool wide) {
     case 10: return pick_adj<10>(f16, wide);
     case 11: return pick_adj<11>(f16, wide);
     case 12: return pick_adj<12>(f16, wide);
+    default: return nullptr;
+  }
+}
+
+GatherFn pick_gather(int F) {
+  switch (F) {
+    case 1: return gather_kernel<1>;
+    case 2: return gather_kernel<2>;
+    case 3: return gather_kernel<3>;
+    case 4: return gather_kernel<4>;
+    case 5: return gather_kernel<5>;
+    case 6: return gather_kernel<6>;
+    case 7: return gather_kernel<7>;
+    case 8: return gather_kernel<8>;
+    case 9: return gather_kernel<9>;
+    case 10: return gather_kernel<10>;
+    case 11: return gather_kernel<11>;
+    case 12: return gather_kernel<12>;
     default: return nullptr;
   }
 }
@@ -330,22 +401,25 @@ RedFn pick_red(int D) {
 
 size_t align256(size_t v) { return (v + 255) & ~static_cast<size_t>(255); }
 
+int64_t gather_blocks(const ClipDev& hc) {
+  return static_cast<int64_t>(hc.T) * ((hc.H + kGatherTile - 1) / kGatherTile) *
+         ((hc.W + kGatherTile - 1) / kGatherTile);
+}
+
 struct Layout {
-  size_t map, contrib, gbpart, gbblk, total;
-  int64_t S;
+  size_t map, rec, gbpart, gbblk, total;
 };
 
 Layout layout(const ClipDev& hc, int64_t n) {
   Layout l{};
-  const int D = hc.F + 2;
-  l.S = static_cast<int64_t>(2 * hc.r + 1) * (2 * hc.r + 1) * (2 * hc.tr + 1);
+  const int D = hc.F + 2, P = hc.F + 3;
   size_t off = 0;
   l.map = off;
   off = align256(off + sizeof(int32_t) * static_cast<size_t>(hc.T) * hc.HW);
-  l.contrib = off;
-  off = align256(off + sizeof(float) * static_cast<size_t>(n) * l.S);
+  l.rec = off;
+  off = align256(off + sizeof(double) * (2 * P + 1) * static_cast<size_t>(n));
   l.gbpart = off;
-  off = align256(off + sizeof(double) * static_cast<size_t>(n) * D);
+  off = align256(off + sizeof(double) * D * static_cast<size_t>(gather_blocks(hc)));
   l.gbblk = off;
   off = align256(off + sizeof(double) * kRedBlocks * D);
   l.total = off;
@@ -363,24 +437,22 @@ unsigned grid_for(int64_t n, int64_t cap) {
 
 size_t backward_scratch_bytes(const ClipDev& hc, int64_t n) { return layout(hc, n).total; }
 
-size_t backward_gather_lds_bytes(const ClipDev& hc) {
-  return sizeof(float) * static_cast<size_t>(kGatherTile + 2 * hc.r) * (2 * hc.r + 2);
-}
+size_t backward_gather_lds_bytes(const ClipDev& hc) { return gather_row_bytes(hc.F, hc.r); }
 
 hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   const ClipDev& hc = *a.host_clip;
   const int F = hc.F, D = F + 2;
-  // 16 lanes per item (one column each) when the window has at most 16
-  // columns: an item's contributions to a window row are then one coalesced
-  // 4(2r+1)-byte store
+  // 16 lanes per item (one column each) when the window has at most 16 columns
   const bool wide = 2 * hc.r + 1 <= kAdjLanesWide;
   AdjFn adj = pick(F, hc.feat_f16 != 0, wide);
+  GatherFn gat = pick_gather(F);
   RedFn rb = pick_red(D);
-  if (!adj || !rb) return hipErrorInvalidValue;
+  if (!adj || !gat || !rb) return hipErrorInvalidValue;
   const Layout l = layout(hc, a.n);
   char* m = static_cast<char*>(a.scratch);
-  BwdDev bd{reinterpret_cast<int32_t*>(m + l.map), reinterpret_cast<float*>(m + l.contrib),
-            reinterpret_cast<double*>(m + l.gbpart), reinterpret_cast<double*>(m + l.gbblk), l.S, a.n};
+  const int64_t gblocks = gather_blocks(hc);
+  BwdDev bd{reinterpret_cast<int32_t*>(m + l.map), reinterpret_cast<double*>(m + l.rec),
+            reinterpret_cast<double*>(m + l.gbpart), reinterpret_cast<double*>(m + l.gbblk), a.n, gblocks};
   const int64_t map_n = static_cast<int64_t>(hc.T) * hc.HW;
   hipLaunchKernelGGL(fill_map_kernel, dim3(grid_for(map_n, 4096)), dim3(256), 0, s, bd.item_map, map_n);
   hipLaunchKernelGGL(map_items_kernel, dim3(grid_for(a.n, 4096)), dim3(256), 0, s, a.clip, a.items, a.n,
@@ -393,10 +465,10 @@ hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   blocks = (blocks + a.dev.xcds - 1) / a.dev.xcds * a.dev.xcds;   // a multiple of the XCDs (see GroupIter)
   hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a.clip, a.items, a.g_alpha, bd,
                      a.dev.xcds);
-  const size_t lds = backward_gather_lds_bytes(hc);
-  const int64_t gblocks = static_cast<int64_t>(hc.T) * hc.H * ((hc.W + kGatherTile - 1) / kGatherTile);
-  hipLaunchKernelGGL(gather_kernel, dim3(static_cast<unsigned>(gblocks)), dim3(kGatherTile), lds, s, a.clip, bd,
-                     a.g_y);
+  const int nbr = gather_band_rows(F, hc.r);
+  const size_t lds = std::max(gather_row_bytes(F, hc.r) * nbr, sizeof(double) * (kGatherThreads / kWave) * D);
+  hipLaunchKernelGGL(gat, dim3(static_cast<unsigned>(gblocks)), dim3(kGatherThreads), lds, s, a.clip, bd, a.g_y,
+                     nbr);
   hipLaunchKernelGGL(rb, dim3(kRedBlocks), dim3(256), 0, s, bd);
   hipLaunchKernelGGL(reduce_gb_final, dim3(1), dim3(64), 0, s, bd, kRedBlocks, D, a.g_b);
   return hipGetLastError();
