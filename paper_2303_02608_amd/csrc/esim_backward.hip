@@ -33,7 +33,7 @@ constexpr int kAdjLanesWide = 16;   // lanes per item, windows of at most 16 col
 constexpr int kRedBlocks = 256;
 constexpr int kGatherTile = 16;     // input pixels of a gather block: 16 x 16, four waves of 8 x 8
 constexpr int kGatherThreads = 256;
-constexpr size_t kGatherLdsBudget = 36864;
+constexpr size_t kGatherLdsBudget = 30720;    // five blocks per CU
 
 struct BwdDev {
   int32_t* item_map;   // [T*HW]
@@ -129,32 +129,34 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
 }
 
 // LDS bytes of one staged item row of the gather (map, record and centre
-// features for each column the block's tile and the window reach, and the
-// row's presence mask).
+// features for each column the block's tile and the window reach).
 size_t gather_row_bytes(int F, int r) {
   const int P = F + 3;
   return static_cast<size_t>(kGatherTile + 2 * r) *
-             (sizeof(int32_t) + sizeof(double) * (2 * P + 1) + sizeof(double) * F) +
-         2 * sizeof(uint64_t);
+         (sizeof(int32_t) + sizeof(double) * (2 * P + 1) + sizeof(double) * F);
 }
 
-// Item rows staged per band (within the LDS budget, at least one).
+// Item rows staged per band: within the LDS budget, at most one staged column
+// per thread, at least one row.
 int gather_band_rows(int F, int r) {
-  return std::max(1, static_cast<int>(kGatherLdsBudget / gather_row_bytes(F, r)));
+  const int by_lds = static_cast<int>(kGatherLdsBudget / gather_row_bytes(F, r));
+  const int by_threads = kGatherThreads / (kGatherTile + 2 * r);
+  return std::max(1, std::min(by_lds, by_threads));
 }
 
 // One block per (input frame tq, 16 x 16 tile of input pixels); wave w owns the
 // 8 x 8 sub-tile (w & 1, w >> 1), lane l the sample (l & 7, l >> 3) in it.  The
 // item rows (yc, tc) that reach the tile are taken in a fixed order (yc
 // ascending, then tc), nbr rows per band: the block stages the band's items
-// (records, centre features, presence masks) for the columns the tile's
-// windows reach, then each wave walks the band's present items in order (rows,
+// (records and centre features; the map entries of the next band are loaded
+// meanwhile) for the columns the tile's windows reach, then each wave walks
+// the band's present items in order (rows,
 // then columns ascending), skipping those outside all of its lanes' windows,
 // and every lane whose window holds the item adds its sample's terms.  The
 // order of every sum is fixed, so g_y and the partials do not depend on
 // scheduling.
 template <int F>
-__global__ void __launch_bounds__(kGatherThreads)
+__global__ void __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(F <= 8 ? 5 : 1)))
 gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ g_y, int nbr) {
   constexpr int D = F + 2;
   constexpr int P = F + 3;
@@ -166,8 +168,7 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   const int ncol = kGatherTile + 2 * r;                        // at most 128 (r <= 56)
   double* srec = sm;                                            // [nbr][ncol][R]
   double* sxcs = srec + static_cast<size_t>(nbr) * ncol * R;    // [nbr][ncol][F]
-  uint64_t* smask = reinterpret_cast<uint64_t*>(sxcs + static_cast<size_t>(nbr) * ncol * F);  // [nbr][2]
-  int32_t* smap = reinterpret_cast<int32_t*>(smask + 2 * nbr);  // [nbr][ncol]
+  int32_t* smap = reinterpret_cast<int32_t*>(sxcs + static_cast<size_t>(nbr) * ncol * F);  // [nbr][ncol]
   const int ntx = (W + kGatherTile - 1) / kGatherTile;
   const int nty = (H + kGatherTile - 1) / kGatherTile;
   int64_t b = blockIdx.x;
@@ -201,21 +202,27 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   const int ntc = t1 - t0 + 1;
   const int yc0 = max(0, by0 - r), yc1 = min(H - 1, by0 + kGatherTile - 1 + r);
   const int nrow = (yc1 - yc0 + 1) * ntc;      // item rows, k = (yc - yc0) * ntc + (tc - t0)
+  // thread q stages column q % ncol of band row q / ncol (nbr * ncol <= threads)
+  const int q = static_cast<int>(threadIdx.x);
+  const int qk = q / ncol, qc = q - qk * ncol;
+  auto map_entry = [&](int k0) -> int32_t {
+    const int k = k0 + qk, x = xs + qc;
+    if (qk >= nbr || k >= nrow || x < 0 || x >= W) return -1;
+    const int yc = yc0 + k / ntc, tc = t0 + k % ntc;
+    return bd.item_map[static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W + x];
+  };
+  int32_t next_it = map_entry(0);
   for (int k0 = 0; k0 < nrow; k0 += nbr) {
     const int nbk = min(nbr, nrow - k0);
+    const int32_t it = next_it;
+    next_it = map_entry(k0 + nbr);             // in flight while this band is staged and walked
     __syncthreads();                           // the previous band's reads are done
-    if (threadIdx.x < 2 * nbk) smask[threadIdx.x] = 0;
-    __syncthreads();
-    for (int q = static_cast<int>(threadIdx.x); q < nbk * ncol; q += kGatherThreads) {
-      const int kk = q / ncol, c = q - kk * ncol;
-      const int k = k0 + kk;
-      const int yc = yc0 + k / ntc, tc = t0 + k % ntc;
-      const int x = xs + c;
-      int32_t it = -1;
-      if (x >= 0 && x < W) it = bd.item_map[static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W + x];
+    if (qk < nbk) {
       smap[q] = it;
       if (it >= 0) {
-        atomicOr(reinterpret_cast<unsigned long long*>(&smask[2 * kk + (c >> 6)]), 1ull << (c & 63));
+        const int k = k0 + qk;
+        const int yc = yc0 + k / ntc, tc = t0 + k % ntc;
+        const int x = xs + qc;
         const double* src = bd.rec + static_cast<int64_t>(it) * R;
 #pragma unroll
         for (int e = 0; e < R; ++e) srec[static_cast<size_t>(q) * R + e] = src[e];
@@ -236,11 +243,11 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
       const double vy = static_cast<double>(dy) * vy_step;
       const double kyy = K * vy;
       for (int word = 0; word < 2; ++word) {
-        // the same mask for every lane: kept in scalar registers
-        const uint64_t mv = smask[2 * kk + word];
-        uint64_t m = static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(mv)))) |
-                     (static_cast<uint64_t>(static_cast<uint32_t>(__builtin_amdgcn_readfirstlane(static_cast<int>(mv >> 32))))
-                      << 32);
+        if (64 * word >= ncol) break;
+        // presence of the row's staged columns 64 word .. 64 word + 63 (a
+        // ballot, the same mask in every lane)
+        const int cl = 64 * word + lane;
+        uint64_t m = __ballot(cl < ncol && smap[kk * ncol + cl] >= 0);
         // the wave's columns wc0 .. wc0 + 7 + 2r of the staged row
         const int lo = wc0 - 64 * word, hi = wc0 + 7 + 2 * r - 64 * word;
         if (hi < 0 || lo > 63) continue;
