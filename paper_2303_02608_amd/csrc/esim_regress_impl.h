@@ -202,18 +202,27 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
         }
       }
 
-      // ---- outputs (the lanes of an item share the writes)
+      // ---- outputs (the lanes of an item share the writes: lane j of the
+      //      group writes components j, j + L, ...; each component's value is
+      //      picked by a select over the L candidates of its round, so a lane
+      //      forms one address per round instead of one per component)
       if (active && a.update_state) {
         if (j == 0) {
           C.st_alpha[my_pix] = static_cast<float>(th[0]);
           C.st_tref[my_pix] = my_t;
         }
 #pragma unroll
-        for (int f = 0; f < F; ++f)
-          if (f % L == j) {
-            C.st_beta[f * C.HW + my_pix] = static_cast<float>(th[3 + f] * C.sf[2 + f]);
+        for (int k = 0; k < (F + L - 1) / L; ++k) {
+          const int f = j + k * L;
+          if (f < F) {
+            double bv = 0.0;
+#pragma unroll
+            for (int ff = k * L; ff < (k + 1) * L && ff < F; ++ff)
+              if (ff == f) bv = th[3 + ff] * C.sf[2 + ff];
+            C.st_beta[f * C.HW + my_pix] = static_cast<float>(bv);
             C.st_xref[f * C.HW + my_pix] = feat_value(C, my_t, f, my_pix);
           }
+        }
       }
       if (active && a.alpha) {
         if (j == 0) {
@@ -232,9 +241,16 @@ __device__ __forceinline__ void regress_group(const RegressArgs& a, int64_t g, i
         }
         if (a.beta) {
 #pragma unroll
-          for (int d = 0; d < D; ++d)
-            if (d % L == j)
-              a.beta[static_cast<int64_t>(d) * a.n_out + idx_out] = static_cast<float>(th[1 + d] * C.sf[d]);
+          for (int k = 0; k < (D + L - 1) / L; ++k) {
+            const int d = j + k * L;
+            if (d < D) {
+              double bv = 0.0;
+#pragma unroll
+              for (int dd = k * L; dd < (k + 1) * L && dd < D; ++dd)
+                if (dd == d) bv = th[1 + dd] * C.sf[dd];
+              a.beta[static_cast<int64_t>(d) * a.n_out + idx_out] = static_cast<float>(bv);
+            }
+          }
         }
       }
     }  // waterfall
