@@ -296,7 +296,10 @@ int esim_events(esim_plan plan, int32_t t, int32_t mode, const int64_t* worklist
  *   ESIM_THRESHOLDED: threshold (Prop. 1) at t >= 1, append the flagged
  *                     pixels' events (sign of dL, during the compaction), and
  *                     regress the flagged pixels, each regression writing its
- *                     model straight into the state.  With an explicit
+ *                     model straight into the state.  In a plan whose clips'
+ *                     windows lie on both sides of 16 columns (2r + 1), the
+ *                     compaction puts the two kinds in separate segments of the
+ *                     plan's work list and each segment gets its own launch.  With an explicit
  *                     esim_threshold the models pass through the plan's
  *                     buffers (one more launch, so that bxy is written too)
  *                     and a last launch sums rmom over the new planes.
