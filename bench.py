@@ -287,25 +287,79 @@ def workload_diff(args, B, synth, Simulator):
 EDGE_PX = 1.5    # an event within this distance of a disc outline is at a moving edge
 
 
-def edge_split(spec, ev, d, r, taus):
-    """Events split by where they are: "edge" (the pixel centre within EDGE_PX
+PLACES = ("edge", "near", "interior")
+
+
+def place_classes(spec, t, x, y, r):
+    """Place of events at (t, x, y): 0 "edge" (the pixel centre within EDGE_PX
     of a disc outline at frame t or t - 1, so a moving outline crossed or
-    touched the pixel), "near" (within r: the regression window reaches an
-    outline) and "interior".  Per class: the events and the share whose
-    nearest same-polarity counterpart is closer than each tau (precision for
-    generated events, recall for reference events)."""
+    touched the pixel), 1 "near" (within r: the regression window reaches an
+    outline), 2 "interior"."""
     import torch
     from paper_2303_02608_amd import synth
-    t, x, y = ev["t"].long(), ev["x"].long(), ev["y"].long()
+    t, x, y = t.long(), x.long(), y.long()
     dist = torch.minimum(synth.boundary_distance(spec, t, x, y),
                          synth.boundary_distance(spec, (t - 1).clamp(min=0), x, y))
+    return torch.where(dist <= EDGE_PX, 0, torch.where(dist <= r, 1, 2))
+
+
+def edge_split(spec, ev, d, r, taus):
+    """Events split by place (place_classes).  Per class: the events and the
+    share whose nearest same-polarity counterpart is closer than each tau
+    (precision for generated events, recall for reference events)."""
+    cls = place_classes(spec, ev["t"], ev["x"], ev["y"], r)
     out = {}
-    for name, m in (("edge", dist <= EDGE_PX), ("near", (dist > EDGE_PX) & (dist <= r)),
-                    ("interior", dist > r)):
+    for k, name in enumerate(PLACES):
+        m = cls == k
         n = int(m.sum())
         out[name] = {"events": n,
                      "share": [round(float((d[m] < tau).double().mean()), 4) if n else None
                                for tau in taus]}
+    return out
+
+
+def prediction_check(sim, spec, r, C):
+    """The thresholded path's predicted change against the change its new
+    regression shows, per event.  A pixel fires when the predicted change
+    dL = beta_ref^T (f_t - x_ref) reaches C; the regression at the event then
+    gives alpha_t, and alpha_t - alpha_ref is the change of the fitted value.
+    Per place: the events, the median of (alpha_t - alpha_ref) / dL, the share
+    whose fitted change is below C / 2 in the predicted direction, and the
+    share whose fitted change has the opposite sign."""
+    import torch
+    from paper_2303_02608_amd import binding as B
+    p, n, T, W = sim.plan, sim.HW, sim.T, sim.W
+    B.regress(p, 0, None, None, n, sim.alpha, sim.beta)
+    B.events(p, 0, B.INIT, None, alpha=sim.alpha, beta=sim.beta, n_out=n)
+    sim.ev.count.zero_()
+    ts, xs, ys, pred, act = [], [], [], [], []
+    for t in range(1, T):
+        B.threshold(p, t, sim.dl, sim.worklist, sim.count)
+        B.regress(p, t, sim.worklist, sim.count, n, sim.alpha, sim.beta)
+        m = int(sim.count[0].item())
+        pix = sim.worklist[:m] & 0xFFFFFFFF
+        pred.append(sim.dl[pix].double())
+        act.append(sim.alpha[:m].double() - sim.state.alpha[pix].double())
+        ts.append(torch.full_like(pix, t))
+        xs.append(pix % W)
+        ys.append(pix // W)
+        B.events(p, t, B.THRESHOLDED, sim.ev, worklist=sim.worklist, count=sim.count,
+                 dl=sim.dl, alpha=sim.alpha, beta=sim.beta, n_out=n)
+    t, x, y = torch.cat(ts), torch.cat(xs), torch.cat(ys)
+    pred, act = torch.cat(pred), torch.cat(act)
+    along = act * torch.sign(pred)                 # fitted change in the predicted direction
+    cls = place_classes(spec, t, x, y, r)
+    out = {}
+    for k, name in enumerate(PLACES):
+        mk = cls == k
+        nk = int(mk.sum())
+        if nk == 0:
+            out[name] = {"events": 0}
+            continue
+        out[name] = {"events": nk,
+                     "median_fitted_over_predicted": round(float((act[mk] / pred[mk]).median()), 4),
+                     "below_half_C": round(float((along[mk] < 0.5 * C).double().mean()), 4),
+                     "opposite_sign": round(float((along[mk] < 0).double().mean()), 4)}
     return out
 
 
@@ -344,6 +398,8 @@ def workload_quality(args, B, synth, Simulator):
                          "F": [round(v, 4) for v in m["F"]], "CD": m["CD"],
                          "precision_by_place": edge_split(spec, evd, m["dg"], cfg["r"], taus),
                          "recall_by_place": edge_split(spec, refd, m["dr"], cfg["r"], taus)}
+            if mode == "thresholded":
+                row[mode]["prediction_by_place"] = prediction_check(sim, spec, cfg["r"], C)
             del sim, run
             log(f"C={C} {mode}: {ms:.2f} ms, {ev['count']} events, F {row[mode]['F']}")
         rows.append(row)
