@@ -179,7 +179,9 @@ typedef struct esim_plan_s* esim_plan;
  * to the device and allocates the compaction workspace.  The plan keeps the
  * pointers, not the data: the caller keeps y, feat and the states alive.
  * Errors: E_INVAL (bad shape, F outside 1..ESIM_MAX_F, bad parameter),
- * E_HIP (allocation or copy failed). */
+ * E_UNSUPPORTED (2^31 pixels or more over the clips, mixed F or feature dtype
+ * or threshold form, a window of 4 GiB or more), E_HIP (allocation or copy
+ * failed). */
 int esim_plan_create(const esim_clip* clips, const esim_params* params,
                      const esim_state* states, int32_t nclips, esim_plan* out);
 int esim_plan_destroy(esim_plan plan);

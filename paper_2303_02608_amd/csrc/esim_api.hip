@@ -317,6 +317,12 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       pl->max_y_bytes = std::max(pl->max_y_bytes, static_cast<uint64_t>(k.T) * cd.HW * 4u);
       pl->host.push_back(cd);
     }
+    if (pix >= (1ll << 31)) {
+      // work-list counts are 32-bit, and the split compaction sums them in the
+      // low half of 64-bit block counts
+      delete pl;
+      return fail(ESIM_E_UNSUPPORTED, "a plan holds fewer than 2^31 pixels over its clips");
+    }
     // the compensated-FP32 instances exist for 4 and 16 lanes only
     if (params[0].precision == ESIM_GRAM_F32C) pl->lanes_dense = 4;
     pl->thr = params[0].threshold;

@@ -96,6 +96,14 @@ def test_bad_shapes_and_params_are_rejected(lib):
                                B.Params(r=5, tr=0, C=0.2, threshold=B.THRESHOLD_NEW_WINDOW).struct(F))
     clips = (B.esim_clip * 2)(clip, clip)
     assert lib.esim_plan_create(clips, pars, None, 2, ctypes.byref(out)) == B.E_UNSUPPORTED
+    # 2^31 pixels or more over the clips (each clip alone is valid: 1.07 G
+    # pixels, one FP16 feature, windows below 4 GiB)
+    big = B.esim_clip(32768, 32767, 1, 1, B.F16, 1, 1)
+    one = B.Params(r=5, tr=0, C=0.2).struct(1)
+    clips = (B.esim_clip * 3)(big, big, big)
+    pars = (B.esim_params * 3)(one, one, one)
+    assert lib.esim_plan_create(clips, pars, None, 3, ctypes.byref(out)) == B.E_UNSUPPORTED
+    assert b"2^31" in lib.esim_last_error()
 
 
 def test_missing_library_fails_loudly(tmp_path, monkeypatch):

@@ -132,3 +132,18 @@ def test_backward_graph_replays(small_clip):
         torch.cuda.synchronize()
         assert torch.equal(gy, ref_y) and torch.equal(gb, ref_b)
         _ = (y * 2).sum().item()
+
+
+@pytest.mark.parametrize("F,r,tr,W,H,seed", [(4, 9, 1, 41, 37, 6), (2, 25, 0, 83, 61, 7)])
+def test_backward_wide_windows(F, r, tr, W, H, seed):
+    """Windows wider than 16 columns: the item kernel runs 4 lanes per item, and
+    at r = 25 a staged item row of the gather spans more than 64 columns (two
+    presence words)."""
+    say(f"backward wide window F={F} r={r} tr={tr} {W}x{H}")
+    T = 4
+    d = synth.random_features_clip(W, H, T, F, seed)
+    rng = np.random.default_rng(seed)
+    items = np.unique(rng.integers(0, T * H * W, size=120))
+    ga = rng.standard_normal(items.size)
+    b = list(rng.uniform(0.7, 1.4, size=F + 2))
+    _check_backward(d["E"].numpy(), d["feat"].numpy(), r, tr, b, items, ga, tag=f"F={F} r={r}")
