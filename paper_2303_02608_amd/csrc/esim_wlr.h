@@ -563,6 +563,24 @@ struct GroupIter {
   }
 };
 
+// Hardware estimates of 1/sqrt(x) and 1/x.
+__device__ __forceinline__ double rsq_approx(double x) { return __builtin_amdgcn_rsq(x); }
+__device__ __forceinline__ float rsq_approx(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rcp_approx(double x) { return __builtin_amdgcn_rcp(x); }
+__device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
+
+// 1/sqrt(x) refined by two Newton steps from the hardware estimate (each step
+// doubles the correct bits; within an ulp or two of the correctly rounded
+// value, a short dependent chain instead of the correctly rounded square root
+// and divide sequences).
+template <class Real>
+__device__ __forceinline__ Real rsq_refined(Real x) {
+  Real y = rsq_approx(x);
+  y = y * fma(Real(-0.5) * x * y, y, Real(1.5));
+  y = y * fma(Real(-0.5) * x * y, y, Real(1.5));
+  return y;
+}
+
 // Solves L L^T x = b with the packed factor (its diagonal holds 1 / L_ii).
 template <int P, class Real>
 __device__ __forceinline__ void chol_solve(const Real (&M)[P * (P + 1) / 2], const Real (&b)[P],
@@ -584,7 +602,8 @@ __device__ __forceinline__ void chol_solve(const Real (&M)[P * (P + 1) / 2], con
 }
 
 // In-place packed Cholesky A = L L^T; the diagonal slots receive 1 / L_ii (the
-// solves multiply by it).  A non-positive pivot yields NaN.
+// solves multiply by it), from the refined reciprocal square root of the
+// pivot.  A non-positive pivot yields NaN.
 template <int P, class Real>
 __device__ __forceinline__ void cholesky_inplace(Real (&M)[P * (P + 1) / 2]) {
 #pragma unroll
@@ -592,8 +611,8 @@ __device__ __forceinline__ void cholesky_inplace(Real (&M)[P * (P + 1) / 2]) {
     Real s = M[tri(c, c)];
 #pragma unroll
     for (int k = 0; k < c; ++k) s -= M[tri(c, k)] * M[tri(c, k)];
-    const Real d = s > Real(0) ? sqrt(s) : static_cast<Real>(__builtin_nan(""));
-    const Real id = Real(1) / d;
+    Real id = rsq_refined(s);
+    id = s > Real(0) ? id : static_cast<Real>(__builtin_nan(""));
     M[tri(c, c)] = id;
 #pragma unroll
     for (int i = c + 1; i < P; ++i) {
@@ -657,10 +676,6 @@ __device__ __forceinline__ Real gram_solve(const Gram<F, Real>& G, const ClipDev
   return iW;
 }
 
-__device__ __forceinline__ double rsq_approx(double x) { return __builtin_amdgcn_rsq(x); }
-__device__ __forceinline__ float rsq_approx(float x) { return __builtin_amdgcn_rsqf(x); }
-__device__ __forceinline__ double rcp_approx(double x) { return __builtin_amdgcn_rcp(x); }
-__device__ __forceinline__ float rcp_approx(float x) { return __builtin_amdgcn_rcpf(x); }
 
 // Turns the packed Cholesky factor of A (diagonal slots holding 1 / L_ii) into
 // the factor of the equilibrated As = S^-1 A S^-1, S^2 = diag(A): row i of L
