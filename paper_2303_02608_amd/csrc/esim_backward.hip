@@ -31,9 +31,12 @@ namespace {
 constexpr int kAdjLanes = 4;        // lanes per item, windows wider than 16 columns
 constexpr int kAdjLanesWide = 16;   // lanes per item, windows of at most 16 columns
 constexpr int kRedBlocks = 256;
+constexpr int kAdjRing = 3;      // rows of window loads in flight in the interior loop
 constexpr int kGatherTile = 16;     // input pixels of a gather block: 16 x 16, four waves of 8 x 8
 constexpr int kGatherThreads = 256;
-constexpr size_t kGatherLdsBudget = 30720;    // five blocks per CU
+constexpr int kGatherWaves = kGatherThreads / kWave;
+constexpr size_t kGatherLdsBudget = 40960;    // four blocks per CU
+constexpr size_t kGatherCountBytes = sizeof(int32_t) * 2 * kGatherWaves;
 
 struct BwdDev {
   int32_t* item_map;   // [T*HW]
@@ -88,9 +91,29 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
     int64_t pix = 0;
     int t = 0;
     const bool active = i < bd.n && item_ok(C, items[i], g_alpha, i, pix, t);
-    if (__ballot(active) == 0) continue;
+    const uint64_t act = __ballot(active);
+    if (act == 0) continue;
+    // Interior waves (every item's window inside the image and the clip) of
+    // the one-column-per-lane instance run the window loop without per-row
+    // validity tests; lanes without an item then take the first item's
+    // geometry with weight 0.
+    const int prow = static_cast<int>(pix / C.W), pcol = static_cast<int>(pix - static_cast<int64_t>(prow) * C.W);
+    const bool inside = prow >= C.r && prow + C.r < C.H && pcol >= C.r && pcol + C.r < C.W &&
+                        t - C.tr >= 0 && t + C.tr < C.T;
+    const bool full = ONE && __ballot(active && !inside) == 0;
+    int64_t gpix = active ? pix : 0;
+    int gt = active ? t : 0;
+    if (full) {
+      const int src = __ffsll(static_cast<unsigned long long>(act)) - 1;
+      const int64_t p0 = __shfl(pix, src);
+      const int t0 = __shfl(t, src);
+      if (!active) {
+        gpix = p0;
+        gt = t0;
+      }
+    }
     ItemGeom<F, F16, double> geo;
-    make_geom(geo, C, active ? pix : 0, active ? t : 0, 0, C.T, active);
+    make_geom(geo, C, gpix, gt, 0, C.T, active);
 
     Gram<F, double> gm;
     auto add = [&](double w, double yd, const double (&v)[F], double vy, int, int, int, bool) {
@@ -99,7 +122,11 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
     if constexpr (ONE) {
       // every lane owns one column of the window (2r + 1 <= L, checked by the launcher)
       gm.zero_onepass();
-      window_loop<F, L, F16, double>(geo, j, [&](double) {}, add, [&](double vx) { gm.fold_onepass(vx); });
+      if (full)
+        window_loop_ring<F, L, F16, kAdjRing>(geo, j, [&](double) {}, add,
+                                              [&](double vx) { gm.fold_onepass(vx); });
+      else
+        window_loop<F, L, F16, double>(geo, j, [&](double) {}, add, [&](double vx) { gm.fold_onepass(vx); });
     } else {
       gm.zero_snap();
       window_loop<F, L, F16, double>(geo, j, [&](double) { gm.pass_begin_snap(); }, add,
@@ -128,36 +155,34 @@ adjoint_kernel(const ClipDev* __restrict__ clips, const int64_t* __restrict__ it
   }
 }
 
-// LDS bytes of one staged item row of the gather (map, record and centre
-// features for each column the block's tile and the window reach).
-size_t gather_row_bytes(int F, int r) {
+// LDS bytes of one staged item of the gather: its record, its centre features
+// (scaled) and its packed position in the block's item region.
+size_t gather_item_bytes(int F) {
   const int P = F + 3;
-  return static_cast<size_t>(kGatherTile + 2 * r) *
-         (sizeof(int32_t) + sizeof(double) * (2 * P + 1) + sizeof(double) * F);
+  return sizeof(double) * (2 * P + 1) + sizeof(double) * F + sizeof(int32_t);
 }
 
-// Item rows staged per band: within the LDS budget, at most one staged column
-// per thread, at least one row.
-int gather_band_rows(int F, int r) {
-  const int by_lds = static_cast<int>(kGatherLdsBudget / gather_row_bytes(F, r));
-  const int by_threads = kGatherThreads / (kGatherTile + 2 * r);
-  return std::max(1, std::min(by_lds, by_threads));
+// Items staged at a time (the LDS budget, less the per-wave counts).
+int gather_capacity(int F) {
+  return static_cast<int>((kGatherLdsBudget - kGatherCountBytes) / gather_item_bytes(F));
 }
 
 // One block per (input frame tq, 16 x 16 tile of input pixels); wave w owns the
-// 8 x 8 sub-tile (w & 1, w >> 1), lane l the sample (l & 7, l >> 3) in it.  The
-// item rows (yc, tc) that reach the tile are taken in a fixed order (yc
-// ascending, then tc), nbr rows per band: the block stages the band's items
-// (records and centre features; the map entries of the next band are loaded
-// meanwhile) for the columns the tile's windows reach, then each wave walks
-// the band's present items in order (rows,
-// then columns ascending), skipping those outside all of its lanes' windows,
-// and every lane whose window holds the item adds its sample's terms.  The
-// order of every sum is fixed, so g_y and the partials do not depend on
-// scheduling.
+// 8 x 8 sub-tile (w & 1, w >> 1), lane l the sample (l & 7, l >> 3) in it.
+// The block's item region is the (frame, row, column) slots whose window can
+// reach the tile: rows yc, frames tc and columns x within r (tr) of it, taken
+// in a fixed order (yc ascending, then tc, then x), 256 slots per step, one per
+// thread.  A step's present items (the frame-pixel map holds their index) are
+// compacted in that order into an LDS buffer of cap items (records, centre
+// features, positions): a wave ballot and prefix, and the four wave counts
+// exchanged through LDS.  When the next item would not fit, every wave walks
+// the buffer in order, skipping the items out of reach of all of its lanes
+// (64 positions tested per ballot), and each lane whose window holds the item
+// adds its sample's terms.  The order of every sum is fixed, so g_y and the
+// partials do not depend on scheduling.
 template <int F>
-__global__ void __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(F <= 8 ? 5 : 1)))
-gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ g_y, int nbr) {
+__global__ void __launch_bounds__(kGatherThreads) __attribute__((amdgpu_waves_per_eu(F <= 8 ? 4 : 1)))
+gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ g_y, int cap) {
   constexpr int D = F + 2;
   constexpr int P = F + 3;
   constexpr int R = 2 * P + 1;
@@ -165,10 +190,11 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   extern __shared__ double sm[];
   const ClipDev& C = clips[0];
   const int r = C.r, tr = C.tr, W = C.W, H = C.H, T = C.T;
-  const int ncol = kGatherTile + 2 * r;                        // at most 128 (r <= 56)
-  double* srec = sm;                                            // [nbr][ncol][R]
-  double* sxcs = srec + static_cast<size_t>(nbr) * ncol * R;    // [nbr][ncol][F]
-  int32_t* smap = reinterpret_cast<int32_t*>(sxcs + static_cast<size_t>(nbr) * ncol * F);  // [nbr][ncol]
+  const int ncol = kGatherTile + 2 * r;                        // at most 66 (r <= 25)
+  double* srec = sm;                                            // [cap][R]
+  double* sxcs = srec + static_cast<size_t>(cap) * R;           // [cap][F]
+  int32_t* spos = reinterpret_cast<int32_t*>(sxcs + static_cast<size_t>(cap) * F);  // [cap] (row << 8) | column
+  int32_t* wcnt = spos + cap;                                   // [2][waves] present items per wave and step
   const int ntx = (W + kGatherTile - 1) / kGatherTile;
   const int nty = (H + kGatherTile - 1) / kGatherTile;
   int64_t b = blockIdx.x;
@@ -182,8 +208,8 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   const int wx0 = bx0 + 8 * (wv & 1), wy0 = by0 + 8 * (wv >> 1);
   const int xq = wx0 + (lane & 7), yq = wy0 + (lane >> 3);
   const bool in = xq < W && yq < H;
-  const int xs = bx0 - r;                      // image column of staged column 0
-  // staged columns whose items reach the wave's columns: wx0 - r .. wx0 + 7 + r
+  const int xs = bx0 - r;                      // image column of region column 0
+  // region columns whose items reach the wave's columns: wc0 .. wc0 + 7 + 2r
   const int wc0 = wx0 - r - xs;
   const int64_t pq = in ? static_cast<int64_t>(yq) * W + xq : 0;
   double fi[F];
@@ -201,94 +227,126 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   const int t0 = max(0, tq - tr), t1 = min(T - 1, tq + tr);
   const int ntc = t1 - t0 + 1;
   const int yc0 = max(0, by0 - r), yc1 = min(H - 1, by0 + kGatherTile - 1 + r);
-  const int nrow = (yc1 - yc0 + 1) * ntc;      // item rows, k = (yc - yc0) * ntc + (tc - t0)
-  // thread q stages column q % ncol of band row q / ncol (nbr * ncol <= threads)
-  const int q = static_cast<int>(threadIdx.x);
-  const int qk = q / ncol, qc = q - qk * ncol;
-  auto map_entry = [&](int k0) -> int32_t {
-    const int k = k0 + qk, x = xs + qc;
-    if (qk >= nbr || k >= nrow || x < 0 || x >= W) return -1;
+  const int nslot = (yc1 - yc0 + 1) * ntc * ncol;   // slot s: row k = s / ncol = (yc - yc0) ntc + tc - t0, column s % ncol
+  auto map_entry = [&](int s) -> int32_t {
+    if (s >= nslot) return -1;
+    const int k = s / ncol, c = s - k * ncol, x = xs + c;
+    if (x < 0 || x >= W) return -1;
     const int yc = yc0 + k / ntc, tc = t0 + k % ntc;
     return bd.item_map[static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W + x];
   };
-  int32_t next_it = map_entry(0);
-  for (int k0 = 0; k0 < nrow; k0 += nbr) {
-    const int nbk = min(nbr, nrow - k0);
-    const int32_t it = next_it;
-    next_it = map_entry(k0 + nbr);             // in flight while this band is staged and walked
-    __syncthreads();                           // the previous band's reads are done
-    if (qk < nbk) {
-      smap[q] = it;
-      if (it >= 0) {
-        const int k = k0 + qk;
+
+  // Walks buffer entries 0 .. n - 1 in order.
+  auto walk = [&](int n) {
+    for (int i0 = 0; i0 < n; i0 += kWave) {
+      const int ii = i0 + lane;
+      const int pp = ii < n ? spos[ii] : 0;
+      const int prow = pp >> 8, pcol = pp & 255;
+      const int yc = yc0 + prow;
+      // items out of reach of every lane of the wave are skipped (ballot)
+      uint64_t m = __ballot(ii < n && yc >= wy0 - r && yc <= wy0 + 7 + r && pcol >= wc0 && pcol <= wc0 + 7 + 2 * r);
+      while (m != 0) {
+        const int bi = __ffsll(static_cast<unsigned long long>(m)) - 1;
+        m &= m - 1;
+        const int pu = __builtin_amdgcn_readlane(pp, bi);
+        const int dy = yq - (yc0 + (pu >> 8));
+        const int dx = xq - (xs + (pu & 255));
+        if (!in || dy < -r || dy > r || dx < -r || dx > r) continue;
+        const int q = i0 + bi;
+        const double* rc = srec + static_cast<size_t>(q) * R;
+        const double* xc = sxcs + static_cast<size_t>(q) * F;
+        // the sample's regressors and weight as the item's window pass forms them
+        const double vy = static_cast<double>(dy) * vy_step;
+        const double kyy = K * vy;
+        const double vx = static_cast<double>(dx) * vx_step;
+        double v[F];
+        double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          v[f] = fma(fi[f], sf[f], -xc[f]);
+          if (f & 1) s1 = fma(v[f], v[f], s1);
+          else s0 = fma(v[f], v[f], s0);
+        }
+        const double arg = fma(s0 + s1, K, fma(kyy, vy, K * vx * vx));
+        const double w = static_cast<double>(__builtin_amdgcn_exp2f(static_cast<float>(arg)));
+        double cs = fma(rc[1], vx, fma(rc[2], vy, rc[0]));
+        double pred = fma(rc[P + 1], vx, fma(rc[P + 2], vy, rc[P]));
+#pragma unroll
+        for (int f = 0; f < F; ++f) {
+          cs = fma(rc[3 + f], v[f], cs);
+          pred = fma(rc[P + 3 + f], v[f], pred);
+        }
+        acc = fma(w, cs, acc);
+        const double kq = w * fma(cs, yi - pred, -rc[2 * P]);
+        gb[0] = fma(kq, vx * vx, gb[0]);
+        gb[1] = fma(kq, vy * vy, gb[1]);
+#pragma unroll
+        for (int f = 0; f < F; ++f) gb[2 + f] = fma(kq, v[f] * v[f], gb[2 + f]);
+      }
+    }
+  };
+
+  // Steps of 256 slots fill the buffer; a walk empties it when a step's items
+  // overflow it (the step is then resumed) and once after the last step.  One
+  // walk site, so that the walk is compiled once.
+  const int tid = static_cast<int>(threadIdx.x);
+  int seq = 0;                                 // items of the region found so far (block-uniform)
+  int base = 0;                                // sequence number of buffer entry 0
+  int par = 0;
+  int s = tid;                                 // this thread's slot of the current step
+  int32_t it = -1;
+  int mine = 0;
+  bool resume = false;
+  int32_t next_it = map_entry(s);
+  for (;;) {
+    int nwalk = 0;                             // block-uniform
+    const bool last = !resume && s - tid >= nslot;
+    if (last) {
+      nwalk = seq - base;
+    } else {
+      if (!resume) {
+        it = next_it;
+        next_it = map_entry(s + kGatherThreads);   // in flight while this step is compacted and staged
+        const uint64_t bal = __ballot(it >= 0);
+        const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(bal >> 32),
+                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0));
+        if (lane == 0) wcnt[par * kGatherWaves + wv] = __popcll(bal);
+        __syncthreads();                       // counts visible
+        int total = 0, off = 0;
+#pragma unroll
+        for (int w2 = 0; w2 < kGatherWaves; ++w2) {
+          const int c = wcnt[par * kGatherWaves + w2];
+          total += c;
+          off += w2 < wv ? c : 0;
+        }
+        par ^= 1;
+        mine = seq + off + below;
+        seq += total;
+      }
+      if (it >= 0 && mine >= base && mine < base + cap) {
+        const int e = mine - base;
+        const int k = s / ncol, c = s - k * ncol;
         const int yc = yc0 + k / ntc, tc = t0 + k % ntc;
-        const int x = xs + qc;
         const double* src = bd.rec + static_cast<int64_t>(it) * R;
 #pragma unroll
-        for (int e = 0; e < R; ++e) srec[static_cast<size_t>(q) * R + e] = src[e];
-        const int64_t p = static_cast<int64_t>(yc) * W + x;
+        for (int j = 0; j < R; ++j) srec[static_cast<size_t>(e) * R + j] = src[j];
+        const int64_t p = static_cast<int64_t>(yc) * W + xs + c;
 #pragma unroll
         for (int f = 0; f < F; ++f)
-          sxcs[static_cast<size_t>(q) * F + f] = static_cast<double>(feat_value(C, tc, f, p)) * sf[f];
+          sxcs[static_cast<size_t>(e) * F + f] = static_cast<double>(feat_value(C, tc, f, p)) * sf[f];
+        spos[e] = ((yc - yc0) << 8) | c;
       }
+      resume = seq > base + cap;
+      if (resume) nwalk = cap;
+      else s += kGatherThreads;
     }
-    __syncthreads();
-    for (int kk = 0; kk < nbk; ++kk) {
-      const int k = k0 + kk;
-      const int yc = yc0 + k / ntc;
-      // rows out of reach of every lane of the wave (wave-uniform)
-      if (yc < wy0 - r || yc > wy0 + 7 + r) continue;
-      const int dy = yq - yc;
-      const bool row_ok = in && dy >= -r && dy <= r;
-      const double vy = static_cast<double>(dy) * vy_step;
-      const double kyy = K * vy;
-      for (int word = 0; word < 2; ++word) {
-        if (64 * word >= ncol) break;
-        // presence of the row's staged columns 64 word .. 64 word + 63 (a
-        // ballot, the same mask in every lane)
-        const int cl = 64 * word + lane;
-        uint64_t m = __ballot(cl < ncol && smap[kk * ncol + cl] >= 0);
-        // the wave's columns wc0 .. wc0 + 7 + 2r of the staged row
-        const int lo = wc0 - 64 * word, hi = wc0 + 7 + 2 * r - 64 * word;
-        if (hi < 0 || lo > 63) continue;
-        if (lo > 0) m &= ~0ull << lo;
-        if (hi < 63) m &= ~0ull >> (63 - hi);
-        while (m != 0) {
-          const int c = __ffsll(static_cast<unsigned long long>(m)) - 1 + 64 * word;
-          m &= m - 1;
-          const int dx = xq - (xs + c);
-          if (!row_ok || dx < -r || dx > r) continue;
-          const int q = kk * ncol + c;
-          const double* rc = srec + static_cast<size_t>(q) * R;
-          const double* xc = sxcs + static_cast<size_t>(q) * F;
-          // the sample's regressors and weight as the item's window pass forms them
-          const double vx = static_cast<double>(dx) * vx_step;
-          double v[F];
-          double s0 = 0.0, s1 = 0.0;
-#pragma unroll
-          for (int f = 0; f < F; ++f) {
-            v[f] = fma(fi[f], sf[f], -xc[f]);
-            if (f & 1) s1 = fma(v[f], v[f], s1);
-            else s0 = fma(v[f], v[f], s0);
-          }
-          const double arg = fma(s0 + s1, K, fma(kyy, vy, K * vx * vx));
-          const double w = static_cast<double>(__builtin_amdgcn_exp2f(static_cast<float>(arg)));
-          double cs = fma(rc[1], vx, fma(rc[2], vy, rc[0]));
-          double pred = fma(rc[P + 1], vx, fma(rc[P + 2], vy, rc[P]));
-#pragma unroll
-          for (int f = 0; f < F; ++f) {
-            cs = fma(rc[3 + f], v[f], cs);
-            pred = fma(rc[P + 3 + f], v[f], pred);
-          }
-          acc = fma(w, cs, acc);
-          const double kq = w * fma(cs, yi - pred, -rc[2 * P]);
-          gb[0] = fma(kq, vx * vx, gb[0]);
-          gb[1] = fma(kq, vy * vy, gb[1]);
-#pragma unroll
-          for (int f = 0; f < F; ++f) gb[2 + f] = fma(kq, v[f] * v[f], gb[2 + f]);
-        }
-      }
+    if (nwalk > 0) {
+      __syncthreads();                         // the buffer is staged
+      walk(nwalk);
+      __syncthreads();                         // its reads are done
+      base += nwalk;
     }
+    if (last) break;
   }
   if (in && acc != 0.0) g_y[static_cast<int64_t>(tq) * C.HW + pq] += static_cast<float>(acc);
   // bandwidth partials of the block: a fixed butterfly inside each wave, then
@@ -297,14 +355,14 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   for (int d = 0; d < D; ++d)
 #pragma unroll
     for (int o = kWave / 2; o > 0; o >>= 1) gb[d] += __shfl_xor(gb[d], o);
-  __syncthreads();                             // the last band's reads are done
+  __syncthreads();                             // the last walk's reads are done
   if (lane == 0)
 #pragma unroll
     for (int d = 0; d < D; ++d) sm[wv * D + d] = gb[d];
   __syncthreads();
   if (threadIdx.x < D) {
     double s = 0.0;
-    for (int w2 = 0; w2 < kGatherThreads / kWave; ++w2) s += sm[w2 * D + threadIdx.x];
+    for (int w2 = 0; w2 < kGatherWaves; ++w2) s += sm[w2 * D + threadIdx.x];
     bd.gbpart[static_cast<int64_t>(blockIdx.x) * D + threadIdx.x] = s * C.sf[threadIdx.x] * C.h;
   }
 }
@@ -444,7 +502,9 @@ unsigned grid_for(int64_t n, int64_t cap) {
 
 size_t backward_scratch_bytes(const ClipDev& hc, int64_t n) { return layout(hc, n).total; }
 
-size_t backward_gather_lds_bytes(const ClipDev& hc) { return gather_row_bytes(hc.F, hc.r); }
+size_t backward_gather_lds_bytes(const ClipDev& hc) {
+  return gather_item_bytes(hc.F) * gather_capacity(hc.F) + kGatherCountBytes;
+}
 
 hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   const ClipDev& hc = *a.host_clip;
@@ -472,10 +532,9 @@ hipError_t launch_backward(const BackwardArgs& a, hipStream_t s) {
   blocks = (blocks + a.dev.xcds - 1) / a.dev.xcds * a.dev.xcds;   // a multiple of the XCDs (see GroupIter)
   hipLaunchKernelGGL(adj, dim3(static_cast<unsigned>(blocks)), dim3(kBlock), 0, s, a.clip, a.items, a.g_alpha, bd,
                      a.dev.xcds);
-  const int nbr = gather_band_rows(F, hc.r);
-  const size_t lds = std::max(gather_row_bytes(F, hc.r) * nbr, sizeof(double) * (kGatherThreads / kWave) * D);
+  const size_t lds = std::max(backward_gather_lds_bytes(hc), sizeof(double) * kGatherWaves * D);
   hipLaunchKernelGGL(gat, dim3(static_cast<unsigned>(gblocks)), dim3(kGatherThreads), lds, s, a.clip, bd, a.g_y,
-                     nbr);
+                     gather_capacity(F));
   hipLaunchKernelGGL(rb, dim3(kRedBlocks), dim3(256), 0, s, bd);
   hipLaunchKernelGGL(reduce_gb_final, dim3(1), dim3(64), 0, s, bd, kRedBlocks, D, a.g_b);
   return hipGetLastError();

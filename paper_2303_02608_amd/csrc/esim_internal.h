@@ -199,8 +199,8 @@ struct BackwardArgs {
   DeviceShape dev;
 };
 size_t backward_scratch_bytes(const ClipDev& hc, int64_t n);
-// LDS of one staged item row of the gather kernel (map, records, centre
-// features); a band of item frames of at most 64 KiB is staged at a time.
+// LDS of the gather kernel's item buffer (records, centre features and
+// positions of the items staged at a time, and the per-wave counts).
 size_t backward_gather_lds_bytes(const ClipDev& hc);
 constexpr size_t kMaxGatherLds = 65536;
 hipError_t launch_backward(const BackwardArgs& a, hipStream_t s);

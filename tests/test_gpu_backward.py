@@ -137,8 +137,8 @@ def test_backward_graph_replays(small_clip):
 @pytest.mark.parametrize("F,r,tr,W,H,seed", [(4, 9, 1, 41, 37, 6), (2, 25, 0, 83, 61, 7)])
 def test_backward_wide_windows(F, r, tr, W, H, seed):
     """Windows wider than 16 columns: the item kernel runs 4 lanes per item, and
-    at r = 25 a staged item row of the gather spans more than 64 columns (two
-    presence words)."""
+    at r = 25 a gather block's item region spans 66 columns and 66 rows (the
+    widest packed positions)."""
     say(f"backward wide window F={F} r={r} tr={tr} {W}x{H}")
     T = 4
     d = synth.random_features_clip(W, H, T, F, seed)
@@ -147,3 +147,20 @@ def test_backward_wide_windows(F, r, tr, W, H, seed):
     ga = rng.standard_normal(items.size)
     b = list(rng.uniform(0.7, 1.4, size=F + 2))
     _check_backward(d["E"].numpy(), d["feat"].numpy(), r, tr, b, items, ga, tag=f"F={F} r={r}")
+
+
+@pytest.mark.parametrize("F,r,tr,seed", [(12, 3, 1, 8), (7, 4, 1, 9)])
+def test_backward_dense_items(F, r, tr, seed):
+    """Every pixel of every frame is an item, so a gather block's region holds
+    far more items than its LDS buffer (117 items at F = 12, 179 at F = 7): the
+    buffer is walked several times within one step of 256 slots, and the step
+    resumes after each walk."""
+    say(f"backward dense items F={F} r={r} tr={tr}")
+    T, H, W = 4, 26, 37
+    d = synth.random_features_clip(W, H, T, F, seed)
+    rng = np.random.default_rng(seed)
+    items = np.arange(T * H * W, dtype=np.int64)
+    ga = rng.standard_normal(items.size)
+    ga[::5] = 0.0
+    b = list(rng.uniform(0.7, 1.4, size=F + 2))
+    _check_backward(d["E"].numpy(), d["feat"].numpy(), r, tr, b, items, ga, tag=f"dense F={F}")
