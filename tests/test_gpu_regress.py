@@ -164,6 +164,43 @@ def test_one_pass_instance(small_clip, r):
            unit_bandwidth=False)
 
 
+@pytest.mark.parametrize("r,f16", [(3, False), (7, False), (5, True)])
+def test_list_equals_dense_one_pass_bitwise(small_clip, r, f16):
+    """A work list of every pixel and a dense launch, both with 16 lanes per
+    item (the one-pass instance), give the same bits: same samples, same
+    order, same sums; only the item mapping differs.  Two clips of different
+    sizes, so that items of both clips share a wave at the clip boundary (the
+    list launch's waterfall over clips)."""
+    E, feat, cfg = small_clip["E"], small_clip["feat"], small_clip["cfg"]
+    if f16:
+        feat = feat.astype(np.float16)
+    p = B.Params(r=r, tr=1, C=cfg["C"], h=1.1, b=[0.9, 1.2, 1.0, 1.1, 0.8, 1.0, 1.3, 0.9, 1.0])
+    say(f"one-pass list vs dense r={r} f16={f16}")
+    y1, fd1 = to_dev(E[:, 1:, 1:], feat[:, :, 1:, 1:])
+    y2, fd2 = to_dev(E[:, 4:, 5:], feat[:, :, 4:, 5:])
+    plan = B.Plan([y1, y2], [fd1, fd2], [p, p])
+    plan.set_schedule(16, 16, 2)
+    n = plan.npix
+    hw1 = y1.shape[1] * y1.shape[2]
+    hw2 = y2.shape[1] * y2.shape[2]
+    items = np.concatenate([np.arange(hw1, dtype=np.int64), (np.int64(1) << 32) | np.arange(hw2, dtype=np.int64)])
+    assert items.size == n and n % 16 != 0 and hw1 % 16 != 0
+    wl = torch.from_numpy(items).cuda()
+    cnt = torch.tensor([n, 0], dtype=torch.int32, device="cuda")
+    for t in (0, 6):
+        out = []
+        for worklist in (None, wl):
+            a = torch.full((n,), 7.0, device="cuda")
+            b = torch.full((plan.D, n), 7.0, device="cuda")
+            R = torch.full((n,), 7.0, device="cuda")
+            B.regress(plan, t, worklist, None if worklist is None else cnt, n, a, b, R)
+            torch.cuda.synchronize()
+            out.append((a, b, R))
+        for u, v in zip(*out):
+            assert torch.equal(u, v), t
+        assert torch.isfinite(out[0][0]).all()
+
+
 def test_f16_features(small_clip):
     cfg = small_clip["cfg"]
     feat = small_clip["feat"].astype(np.float16)
