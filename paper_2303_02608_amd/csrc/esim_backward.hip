@@ -36,7 +36,8 @@ constexpr int kGatherTile = 16;     // input pixels of a gather block: 16 x 16, 
 constexpr int kGatherThreads = 256;
 constexpr int kGatherWaves = kGatherThreads / kWave;
 constexpr size_t kGatherLdsBudget = 40960;    // four blocks per CU
-constexpr size_t kGatherCountBytes = sizeof(int32_t) * 2 * kGatherWaves;
+constexpr int kGatherSlots = 4;              // region slots per thread and step of the gather's scan
+constexpr size_t kGatherCountBytes = sizeof(int32_t) * 2 * kGatherSlots * kGatherWaves;
 
 struct BwdDev {
   int32_t* item_map;   // [T*HW]
@@ -171,8 +172,8 @@ int gather_capacity(int F) {
 // 8 x 8 sub-tile (w & 1, w >> 1), lane l the sample (l & 7, l >> 3) in it.
 // The block's item region is the (frame, row, column) slots whose window can
 // reach the tile: rows yc, frames tc and columns x within r (tr) of it, taken
-// in a fixed order (yc ascending, then tc, then x), 256 slots per step, one per
-// thread.  A step's present items (the frame-pixel map holds their index) are
+// in a fixed order (tc ascending, then yc, then x), 1024 slots per step, four
+// per thread.  A step's present items (the frame-pixel map holds their index) are
 // compacted in that order into an LDS buffer of cap items (records, centre
 // features, positions): a wave ballot and prefix, and the four wave counts
 // exchanged through LDS.  When the next item would not fit, every wave walks
@@ -194,7 +195,7 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   double* srec = sm;                                            // [cap][R]
   double* sxcs = srec + static_cast<size_t>(cap) * R;           // [cap][F]
   int32_t* spos = reinterpret_cast<int32_t*>(sxcs + static_cast<size_t>(cap) * F);  // [cap] (row << 8) | column
-  int32_t* wcnt = spos + cap;                                   // [2][waves] present items per wave and step
+  int32_t* wcnt = spos + cap;                                   // [2][slots][waves] present items per wave and step
   const int ntx = (W + kGatherTile - 1) / kGatherTile;
   const int nty = (H + kGatherTile - 1) / kGatherTile;
   int64_t b = blockIdx.x;
@@ -227,12 +228,16 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   const int t0 = max(0, tq - tr), t1 = min(T - 1, tq + tr);
   const int ntc = t1 - t0 + 1;
   const int yc0 = max(0, by0 - r), yc1 = min(H - 1, by0 + kGatherTile - 1 + r);
-  const int nslot = (yc1 - yc0 + 1) * ntc * ncol;   // slot s: row k = s / ncol = (yc - yc0) ntc + tc - t0, column s % ncol
+  const int nry = yc1 - yc0 + 1;
+  // slot s: row k = s / ncol = (tc - t0) nry + yc - yc0, column s % ncol (frame
+  // by frame, so that every buffer holds items of all the tile's rows and all
+  // four waves have work in every walk)
+  const int nslot = nry * ntc * ncol;
   auto map_entry = [&](int s) -> int32_t {
     if (s >= nslot) return -1;
     const int k = s / ncol, c = s - k * ncol, x = xs + c;
     if (x < 0 || x >= W) return -1;
-    const int yc = yc0 + k / ntc, tc = t0 + k % ntc;
+    const int yc = yc0 + k % nry, tc = t0 + k / nry;
     return bd.item_map[static_cast<int64_t>(tc) * C.HW + static_cast<int64_t>(yc) * W + x];
   };
 
@@ -293,11 +298,17 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
   int seq = 0;                                 // items of the region found so far (block-uniform)
   int base = 0;                                // sequence number of buffer entry 0
   int par = 0;
-  int s = tid;                                 // this thread's slot of the current step
-  int32_t it = -1;
-  int mine = 0;
+  int s = tid;                                 // this thread's first slot of the current step
+  int32_t it[kGatherSlots];
+  int mine[kGatherSlots];
   bool resume = false;
-  int32_t next_it = map_entry(s);
+  int32_t next_it[kGatherSlots];
+#pragma unroll
+  for (int u = 0; u < kGatherSlots; ++u) {
+    it[u] = -1;
+    mine[u] = 0;
+    next_it[u] = map_entry(s + u * kGatherThreads);
+  }
   for (;;) {
     int nwalk = 0;                             // block-uniform
     const bool last = !resume && s - tid >= nslot;
@@ -305,40 +316,52 @@ gather_kernel(const ClipDev* __restrict__ clips, BwdDev bd, float* __restrict__ 
       nwalk = seq - base;
     } else {
       if (!resume) {
-        it = next_it;
-        next_it = map_entry(s + kGatherThreads);   // in flight while this step is compacted and staged
-        const uint64_t bal = __ballot(it >= 0);
-        const int below = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(bal >> 32),
-                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0));
-        if (lane == 0) wcnt[par * kGatherWaves + wv] = __popcll(bal);
-        __syncthreads();                       // counts visible
-        int total = 0, off = 0;
+        int below[kGatherSlots];
 #pragma unroll
-        for (int w2 = 0; w2 < kGatherWaves; ++w2) {
-          const int c = wcnt[par * kGatherWaves + w2];
-          total += c;
-          off += w2 < wv ? c : 0;
+        for (int u = 0; u < kGatherSlots; ++u) {
+          it[u] = next_it[u];
+          // in flight while this step is compacted and staged
+          next_it[u] = map_entry(s + (kGatherSlots + u) * kGatherThreads);
+          const uint64_t bal = __ballot(it[u] >= 0);
+          below[u] = __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(bal >> 32),
+                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bal), 0));
+          if (lane == 0) wcnt[(par * kGatherSlots + u) * kGatherWaves + wv] = __popcll(bal);
+        }
+        __syncthreads();                       // counts visible
+#pragma unroll
+        for (int u = 0; u < kGatherSlots; ++u) {
+          int total = 0, off = 0;
+#pragma unroll
+          for (int w2 = 0; w2 < kGatherWaves; ++w2) {
+            const int c = wcnt[(par * kGatherSlots + u) * kGatherWaves + w2];
+            total += c;
+            off += w2 < wv ? c : 0;
+          }
+          mine[u] = seq + off + below[u];
+          seq += total;
         }
         par ^= 1;
-        mine = seq + off + below;
-        seq += total;
       }
-      if (it >= 0 && mine >= base && mine < base + cap) {
-        const int e = mine - base;
-        const int k = s / ncol, c = s - k * ncol;
-        const int yc = yc0 + k / ntc, tc = t0 + k % ntc;
-        const double* src = bd.rec + static_cast<int64_t>(it) * R;
 #pragma unroll
-        for (int j = 0; j < R; ++j) srec[static_cast<size_t>(e) * R + j] = src[j];
-        const int64_t p = static_cast<int64_t>(yc) * W + xs + c;
+      for (int u = 0; u < kGatherSlots; ++u) {
+        if (it[u] >= 0 && mine[u] >= base && mine[u] < base + cap) {
+          const int e = mine[u] - base;
+          const int su = s + u * kGatherThreads;
+          const int k = su / ncol, c = su - k * ncol;
+          const int yc = yc0 + k % nry, tc = t0 + k / nry;
+          const double* src = bd.rec + static_cast<int64_t>(it[u]) * R;
 #pragma unroll
-        for (int f = 0; f < F; ++f)
-          sxcs[static_cast<size_t>(e) * F + f] = static_cast<double>(feat_value(C, tc, f, p)) * sf[f];
-        spos[e] = ((yc - yc0) << 8) | c;
+          for (int j = 0; j < R; ++j) srec[static_cast<size_t>(e) * R + j] = src[j];
+          const int64_t p = static_cast<int64_t>(yc) * W + xs + c;
+#pragma unroll
+          for (int f = 0; f < F; ++f)
+            sxcs[static_cast<size_t>(e) * F + f] = static_cast<double>(feat_value(C, tc, f, p)) * sf[f];
+          spos[e] = ((yc - yc0) << 8) | c;
+        }
       }
       resume = seq > base + cap;
       if (resume) nwalk = cap;
-      else s += kGatherThreads;
+      else s += kGatherSlots * kGatherThreads;
     }
     if (nwalk > 0) {
       __syncthreads();                         // the buffer is staged
