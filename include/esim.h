@@ -184,6 +184,8 @@ typedef struct esim_plan_s* esim_plan;
  * failed). */
 int esim_plan_create(const esim_clip* clips, const esim_params* params,
                      const esim_state* states, int32_t nclips, esim_plan* out);
+/* Frees the plan's device buffers and the plan (a null plan is accepted).
+ * Returns E_HIP if a free fails; the plan is released in any case. */
 int esim_plan_destroy(esim_plan plan);
 
 /* Total pixels over the plan's clips (sum of H*W): the length of dl, of dense

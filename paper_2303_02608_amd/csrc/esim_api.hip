@@ -424,7 +424,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       e = hipMemcpy(pl->xcd_bounds, xb.data(), sizeof(int64_t) * xb.size(), hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
-      hipFree(pl->ws_mem);
+      (void)hipFree(pl->ws_mem);   // the upload's error is the one reported
       delete pl;
       return hip_check(e, "plan upload");
     }
@@ -441,7 +441,7 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
       if (pl->thr != ESIM_THRESHOLD_CLOSED) so = align(so + sizeof(float) * (pl->F + 2) * pix);
       e = hipMalloc(&pl->step_mem, so);
       if (e != hipSuccess) {
-        hipFree(pl->ws_mem);
+        (void)hipFree(pl->ws_mem);   // the allocation's error is the one reported
         delete pl;
         return hip_check(e, "hipMalloc(step buffers)");
       }
@@ -462,10 +462,14 @@ int esim_plan_create(const esim_clip* clips, const esim_params* params, const es
 
 int esim_plan_destroy(esim_plan pl) {
   if (!pl) return ok();
-  if (pl->ws_mem) hipFree(pl->ws_mem);
-  if (pl->step_mem) hipFree(pl->step_mem);
-  delete pl;
-  return ok();
+  hipError_t e = hipSuccess;
+  if (pl->ws_mem) e = hipFree(pl->ws_mem);
+  if (pl->step_mem) {
+    const hipError_t e2 = hipFree(pl->step_mem);
+    if (e == hipSuccess) e = e2;
+  }
+  delete pl;   // the plan is gone either way; a failed free is reported
+  return hip_check(e, "hipFree(plan buffers)");
 }
 
 int64_t esim_plan_pixels(esim_plan pl) { return pl ? pl->npix : -1; }
