@@ -175,8 +175,8 @@ int gather_capacity(int F) {
 // in a fixed order (tc ascending, then yc, then x), 1024 slots per step, four
 // per thread.  A step's present items (the frame-pixel map holds their index) are
 // compacted in that order into an LDS buffer of cap items (records, centre
-// features, positions): a wave ballot and prefix, and the four wave counts
-// exchanged through LDS.  When the next item would not fit, every wave walks
+// features, positions): a wave ballot and prefix per set of 256 slots, and the
+// waves' counts exchanged through LDS.  When the next item would not fit, every wave walks
 // the buffer in order, skipping the items out of reach of all of its lanes
 // (64 positions tested per ballot), and each lane whose window holds the item
 // adds its sample's terms.  The order of every sum is fixed, so g_y and the
